@@ -1,0 +1,468 @@
+/*
+ * FP64 CPU oracle for multi-stage sketched plug-and-play fan-beam CT
+ * (Tang, "Accelerating Plug-and-Play Image Reconstruction via Multi-Stage
+ * Sketched Gradients", arXiv:2203.07308).
+ *
+ * TEST INFRASTRUCTURE. This file is the plain, slow reference against which the
+ * GPU library is checked. Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load it. It shares no code, header, table or
+ * helper with the GPU library, and the GPU library never calls it.
+ *
+ * Everything is IEEE double precision, written to be read against the paper:
+ *   - measurement model b = A x + w ........................ Sec. 1, Eq. (1)
+ *   - least-squares data term and its gradient A^T(Ax - b) .. Sec. 1, Eq. (2); Sec. 2.1, Eq. (5)
+ *   - sketched objective f(b, A_s S(x)) ..................... Sec. 2.1, Eq. (4)
+ *   - sketched gradient U(A_s^T A_s S(x) - A_s^T b) ......... Sec. 2.1, Eq. (6)
+ *   - minibatch (view subset) form with M_k ................. Sec. 2.1, Eq. (7)
+ *   - PnP-MS2G iteration (sketch, gradient, step, relaxed
+ *     denoiser, momentum) ................................... Sec. 2.1, Algorithm 1
+ *   - TV-prox as the denoiser D ............................. Sec. 2.1 (denoiser list after Eq. (5))
+ *   - step eta = 1/L, momentum a_i = (i-1)/(i+3), alpha = 1 .. Sec. 3, experimental settings
+ *
+ * The paper fixes neither the projector nor the fan geometry nor the TV-prox
+ * algorithm. The readings used here (all stated again where they are applied):
+ *   geometry: pixel (r,c) centre ((c-(nx-1)/2) h, (r-(ny-1)/2) h), stored at
+ *     x[r*nx + c]; view k at angle beta = angle0 + k*angle_step; source
+ *     S = sod (cos b, sin b); detector centre C = (sod - sdd)(cos b, sin b);
+ *     detector direction e_u = (-sin b, cos b); bin j centre
+ *     Q_j = C + ((j - (B-1)/2) pitch + det_offset) e_u; ray direction d = Q_j - S.
+ *   projector: Joseph's method, one ray per bin centre. A ray is x-major when
+ *     |d_x| >= |d_y|; it is then sampled on every pixel-centre column by linear
+ *     interpolation between the two nearest pixel-centre rows, pixels outside
+ *     the grid being zero, and the sum is weighted by h |d| / |d_x|. y-major rays
+ *     swap the roles of rows and columns.
+ *   sketch S = average pooling D_f over f x f blocks; upsampler U = D_f^T
+ *     (replicate, divide by f^2); A_s = the same projector on the (n/f) grid
+ *     with pixel size f h.
+ *   denoiser: Chambolle's dual projection iteration for isotropic TV with
+ *     forward differences and Neumann boundary, p^0 = 0 on every call.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t nx, ny;        /* full-resolution grid (pixels) */
+    double pixel_mm;       /* full-resolution pixel size h */
+    int32_t n_views, n_bins;
+    double sod_mm, sdd_mm; /* source-to-isocentre, source-to-detector */
+    double det_pitch_mm, det_offset_mm;
+    double angle0_rad, angle_step_rad;
+} orc_geom;
+
+/* ------------------------------------------------------------------------- */
+/* Geometry                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Source position and ray direction of (view k, bin j). */
+static void orc_ray(const orc_geom* g, int k, int j, double* sx, double* sy, double* dx,
+                    double* dy) {
+    double beta = g->angle0_rad + (double)k * g->angle_step_rad;
+    double cb = cos(beta), sb = sin(beta);
+    double src_x = g->sod_mm * cb, src_y = g->sod_mm * sb;
+    double cen_x = (g->sod_mm - g->sdd_mm) * cb, cen_y = (g->sod_mm - g->sdd_mm) * sb;
+    double u = ((double)j - 0.5 * (double)(g->n_bins - 1)) * g->det_pitch_mm + g->det_offset_mm;
+    double qx = cen_x + u * (-sb), qy = cen_y + u * cb;
+    *sx = src_x;
+    *sy = src_y;
+    *dx = qx - src_x;
+    *dy = qy - src_y;
+}
+
+void orc_ray_geometry(const orc_geom* g, int k, int j, double* out4) {
+    orc_ray(g, k, j, &out4[0], &out4[1], &out4[2], &out4[3]);
+}
+
+/* Pixel value with zero outside the grid. */
+static double pix(const double* x, int nx, int ny, int r, int c) {
+    if (r < 0 || r >= ny || c < 0 || c >= nx) return 0.0;
+    return x[(size_t)r * nx + c];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Joseph projector on a grid of nxs x nys pixels of size hs                  */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * One ray of the forward operator A_s (Sec. 1, Eq. (1); Sec. 2.1, Eq. (4)).
+ * If count != NULL it receives the number of interpolation samples with at
+ * least one in-grid tap of nonzero weight.
+ */
+static double joseph_ray(const orc_geom* g, int k, int j, int nxs, int nys, double hs,
+                         const double* x, long* count) {
+    double sx, sy, dx, dy;
+    orc_ray(g, k, j, &sx, &sy, &dx, &dy);
+    double len = sqrt(dx * dx + dy * dy);
+    double acc = 0.0;
+    long n_in = 0;
+    if (fabs(dx) >= fabs(dy)) {
+        /* x-major: one sample on every pixel-centre column */
+        for (int c = 0; c < nxs; ++c) {
+            double xc = ((double)c - 0.5 * (double)(nxs - 1)) * hs;
+            double t = (xc - sx) / dx;
+            double yv = sy + t * dy;
+            double rho = yv / hs + 0.5 * (double)(nys - 1);
+            double r0 = floor(rho);
+            double w = rho - r0;
+            int ir = (int)r0;
+            if (rho > -1.0 && rho < (double)nys) n_in++;
+            if (rho > -2.0 && rho < (double)nys + 1.0)
+                acc += (1.0 - w) * pix(x, nxs, nys, ir, c) + w * pix(x, nxs, nys, ir + 1, c);
+        }
+        acc *= hs * len / fabs(dx);
+    } else {
+        /* y-major: one sample on every pixel-centre row */
+        for (int r = 0; r < nys; ++r) {
+            double yr = ((double)r - 0.5 * (double)(nys - 1)) * hs;
+            double t = (yr - sy) / dy;
+            double xv = sx + t * dx;
+            double kap = xv / hs + 0.5 * (double)(nxs - 1);
+            double c0 = floor(kap);
+            double w = kap - c0;
+            int ic = (int)c0;
+            if (kap > -1.0 && kap < (double)nxs) n_in++;
+            if (kap > -2.0 && kap < (double)nxs + 1.0)
+                acc += (1.0 - w) * pix(x, nxs, nys, r, ic) + w * pix(x, nxs, nys, r, ic + 1);
+        }
+        acc *= hs * len / fabs(dy);
+    }
+    if (count) *count = n_in;
+    return acc;
+}
+
+/*
+ * Transpose of one ray: spread val along the ray with the identical weights.
+ * Adds into xt (nys x nxs).
+ */
+static void joseph_ray_adjoint(const orc_geom* g, int k, int j, int nxs, int nys, double hs,
+                               double val, double* xt) {
+    double sx, sy, dx, dy;
+    orc_ray(g, k, j, &sx, &sy, &dx, &dy);
+    double len = sqrt(dx * dx + dy * dy);
+    if (fabs(dx) >= fabs(dy)) {
+        double wl = val * hs * len / fabs(dx);
+        for (int c = 0; c < nxs; ++c) {
+            double xc = ((double)c - 0.5 * (double)(nxs - 1)) * hs;
+            double t = (xc - sx) / dx;
+            double yv = sy + t * dy;
+            double rho = yv / hs + 0.5 * (double)(nys - 1);
+            if (!(rho > -2.0 && rho < (double)nys + 1.0)) continue;
+            double r0 = floor(rho);
+            double w = rho - r0;
+            int ir = (int)r0;
+            if (ir >= 0 && ir < nys) xt[(size_t)ir * nxs + c] += (1.0 - w) * wl;
+            if (ir + 1 >= 0 && ir + 1 < nys) xt[(size_t)(ir + 1) * nxs + c] += w * wl;
+        }
+    } else {
+        double wl = val * hs * len / fabs(dy);
+        for (int r = 0; r < nys; ++r) {
+            double yr = ((double)r - 0.5 * (double)(nys - 1)) * hs;
+            double t = (yr - sy) / dy;
+            double xv = sx + t * dx;
+            double kap = xv / hs + 0.5 * (double)(nxs - 1);
+            if (!(kap > -2.0 && kap < (double)nxs + 1.0)) continue;
+            double c0 = floor(kap);
+            double w = kap - c0;
+            int ic = (int)c0;
+            if (ic >= 0 && ic < nxs) xt[(size_t)r * nxs + ic] += (1.0 - w) * wl;
+            if (ic + 1 >= 0 && ic + 1 < nxs) xt[(size_t)r * nxs + ic + 1] += w * wl;
+        }
+    }
+}
+
+static int view_of(const int32_t* views, int i) { return views ? views[i] : i; }
+
+/*
+ * Forward projection y = M A_s x on the grid coarsened by f.
+ * x: (ny/f) x (nx/f); y: n_sel x n_bins, rows in the order of `views`
+ * (views == NULL selects every view in order, n_sel = n_views).
+ */
+void orc_fp(const orc_geom* g, int f, const double* x, double* y, const int32_t* views,
+            int n_sel) {
+    int nxs = g->nx / f, nys = g->ny / f;
+    double hs = g->pixel_mm * f;
+    int nb = g->n_bins;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < n_sel; ++i) {
+        int k = view_of(views, i);
+        for (int j = 0; j < nb; ++j)
+            y[(size_t)i * nb + j] = joseph_ray(g, k, j, nxs, nys, hs, x, NULL);
+    }
+}
+
+/* Number of in-grid Joseph samples of M A_s (used to state projector work). */
+long orc_count_samples(const orc_geom* g, int f, const int32_t* views, int n_sel) {
+    int nxs = g->nx / f, nys = g->ny / f;
+    double hs = g->pixel_mm * f;
+    long total = 0;
+    double* zero = (double*)calloc((size_t)nxs * nys, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
+    for (int i = 0; i < n_sel; ++i) {
+        int k = view_of(views, i);
+        for (int j = 0; j < g->n_bins; ++j) {
+            long c = 0;
+            joseph_ray(g, k, j, nxs, nys, hs, zero, &c);
+            total += c;
+        }
+    }
+    free(zero);
+    return total;
+}
+
+/*
+ * Backprojection x = scale * (M A_s)^T y by scattering the forward weights.
+ * The views are split into a fixed number of chunks, each accumulated in its
+ * own buffer, and the chunks are summed in order, so the result does not depend
+ * on the number of threads.
+ */
+#define ORC_BP_CHUNKS 16
+void orc_bp(const orc_geom* g, int f, const double* y, double* x, const int32_t* views,
+            int n_sel, double scale) {
+    int nxs = g->nx / f, nys = g->ny / f;
+    double hs = g->pixel_mm * f;
+    int nb = g->n_bins;
+    size_t npix = (size_t)nxs * nys;
+    double* part = (double*)calloc(npix * ORC_BP_CHUNKS, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int ch = 0; ch < ORC_BP_CHUNKS; ++ch) {
+        double* acc = part + (size_t)ch * npix;
+        for (int i = ch; i < n_sel; i += ORC_BP_CHUNKS) {
+            int k = view_of(views, i);
+            for (int j = 0; j < nb; ++j) {
+                double v = y[(size_t)i * nb + j];
+                if (v != 0.0) joseph_ray_adjoint(g, k, j, nxs, nys, hs, v, acc);
+            }
+        }
+    }
+    for (size_t p = 0; p < npix; ++p) {
+        double s = 0.0;
+        for (int ch = 0; ch < ORC_BP_CHUNKS; ++ch) s += part[(size_t)ch * npix + p];
+        x[p] = scale * s;
+    }
+    free(part);
+}
+
+/*
+ * Dense matrix of M A_s for tiny grids, built column by column: column m is
+ * the projection of the m-th unit image. A: (n_sel*n_bins) x (nxs*nys), row-major.
+ */
+void orc_dense_matrix(const orc_geom* g, int f, const int32_t* views, int n_sel, double* A) {
+    int nxs = g->nx / f, nys = g->ny / f;
+    size_t d = (size_t)nxs * nys, n = (size_t)n_sel * g->n_bins;
+    double* e = (double*)calloc(d, sizeof(double));
+    double* col = (double*)malloc(n * sizeof(double));
+    for (size_t m = 0; m < d; ++m) {
+        e[m] = 1.0;
+        orc_fp(g, f, e, col, views, n_sel);
+        for (size_t i = 0; i < n; ++i) A[i * d + m] = col[i];
+        e[m] = 0.0;
+    }
+    free(e);
+    free(col);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sketch S = D_f (f x f average pooling) and upsampler U = D_f^T             */
+/* ------------------------------------------------------------------------- */
+
+void orc_down(const double* x, int nx, int ny, int f, double* v) {
+    int nxs = nx / f, nys = ny / f;
+    for (int R = 0; R < nys; ++R)
+        for (int C = 0; C < nxs; ++C) {
+            double s = 0.0;
+            for (int a = 0; a < f; ++a)
+                for (int b = 0; b < f; ++b) s += x[(size_t)(f * R + a) * nx + (f * C + b)];
+            v[(size_t)R * nxs + C] = s / (double)(f * f);
+        }
+}
+
+void orc_up(const double* v, int nxs, int nys, int f, double* x) {
+    int nx = nxs * f, ny = nys * f;
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c < nx; ++c) x[(size_t)r * nx + c] = v[(size_t)(r / f) * nxs + c / f] / (double)(f * f);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sketched (minibatch) gradient, Sec. 2.1, Eqs. (6)-(7)                      */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * g = sigma * U (M A_s)^T (M A_s S(y) - M b) for the data term 1/2 ||A_s S y - b||^2.
+ * b is the full sinogram (n_views x n_bins); M keeps the rows of `views`.
+ * y and g are full-resolution (ny x nx).
+ */
+void orc_grad(const orc_geom* g, int f, const double* y, const double* b, const int32_t* views,
+              int n_sel, double sigma, double* grad) {
+    int nx = g->nx, ny = g->ny, nxs = nx / f, nys = ny / f, nb = g->n_bins;
+    size_t ds = (size_t)nxs * nys, ns = (size_t)n_sel * nb;
+    double* v = (double*)malloc(ds * sizeof(double));
+    double* r = (double*)malloc(ns * sizeof(double));
+    double* gs = (double*)malloc(ds * sizeof(double));
+    orc_down(y, nx, ny, f, v);
+    orc_fp(g, f, v, r, views, n_sel);
+    for (int i = 0; i < n_sel; ++i) {
+        int k = view_of(views, i);
+        for (int j = 0; j < nb; ++j) r[(size_t)i * nb + j] -= b[(size_t)k * nb + j];
+    }
+    orc_bp(g, f, r, gs, views, n_sel, sigma);
+    orc_up(gs, nxs, nys, f, grad);
+    free(v);
+    free(r);
+    free(gs);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Denoiser: TV-prox by Chambolle's dual projection                           */
+/* ------------------------------------------------------------------------- */
+
+/* (div p)_{r,c} with p1 the row-direction and p2 the column-direction component. */
+static void tv_div(const double* p1, const double* p2, int nx, int ny, double* dv) {
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            size_t i = (size_t)r * nx + c;
+            double s = 0.0;
+            if (r < ny - 1) s += p1[i];
+            if (r > 0) s -= p1[i - nx];
+            if (c < nx - 1) s += p2[i];
+            if (c > 0) s -= p2[i - 1];
+            dv[i] = s;
+        }
+}
+
+/*
+ * x = argmin_u 1/2 ||u - z||^2 + lambda TV(u), approximated by n_iter steps of
+ *   p <- (p + tau grad(div p - z/lambda)) / (1 + tau |grad(div p - z/lambda)|)
+ * from p = 0, then x = z - lambda div p. lambda == 0 returns z.
+ */
+void orc_tv_prox(const double* z, int nx, int ny, double lambda, int n_iter, double tau,
+                 double* x) {
+    size_t n = (size_t)nx * ny;
+    if (lambda == 0.0) {
+        memcpy(x, z, n * sizeof(double));
+        return;
+    }
+    double* p1 = (double*)calloc(n, sizeof(double));
+    double* p2 = (double*)calloc(n, sizeof(double));
+    double* dv = (double*)calloc(n, sizeof(double));
+    double* u = (double*)malloc(n * sizeof(double));
+    for (int it = 0; it < n_iter; ++it) {
+        tv_div(p1, p2, nx, ny, dv);
+        for (size_t i = 0; i < n; ++i) u[i] = dv[i] - z[i] / lambda;
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)r * nx + c;
+                double q1 = (r < ny - 1) ? u[i + nx] - u[i] : 0.0;
+                double q2 = (c < nx - 1) ? u[i + 1] - u[i] : 0.0;
+                double mag = sqrt(q1 * q1 + q2 * q2);
+                double den = 1.0 + tau * mag;
+                p1[i] = (p1[i] + tau * q1) / den;
+                p2[i] = (p2[i] + tau * q2) / den;
+            }
+    }
+    tv_div(p1, p2, nx, ny, dv);
+    for (size_t i = 0; i < n; ++i) x[i] = z[i] - lambda * dv[i];
+    free(p1);
+    free(p2);
+    free(dv);
+    free(u);
+}
+
+/* ------------------------------------------------------------------------- */
+/* PnP-MS2G loop, Sec. 2.1 Algorithm 1                                        */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Runs T iterations from x_0 = y_0 = x0. Iteration t (1-based) uses
+ *   factor[t-1]   pooling factor f of its stage,
+ *   views + view_off[t-1], n_sel[t-1]   the minibatch M_t (view list),
+ *   sigma[t-1]    minibatch scale (n_views / n_sel for an unbiased estimate),
+ *   eta[t-1], a[t-1]   step and momentum,
+ * and computes
+ *   z   = y_{t-1} - eta_t * G(y_{t-1})
+ *   x_t = (1 - alpha) z + alpha TV(z)
+ *   y_t = x_t + a_t (x_t - x_{t-1}).
+ * history (optional): T x (ny*nx) iterates x_t. x_out: x_T.
+ */
+void orc_pnp_run(const orc_geom* g, int T, const int32_t* factor, const int32_t* views,
+                 const int32_t* view_off, const int32_t* n_sel, const double* sigma,
+                 const double* eta, const double* a, double alpha, double lambda, int tv_iters,
+                 double tau, const double* b, const double* x0, double* x_out, double* history) {
+    size_t n = (size_t)g->nx * g->ny;
+    double* x_prev = (double*)malloc(n * sizeof(double));
+    double* y = (double*)malloc(n * sizeof(double));
+    double* z = (double*)malloc(n * sizeof(double));
+    double* x = (double*)malloc(n * sizeof(double));
+    double* gr = (double*)malloc(n * sizeof(double));
+    memcpy(x_prev, x0, n * sizeof(double));
+    memcpy(y, x0, n * sizeof(double));
+    for (int t = 0; t < T; ++t) {
+        const int32_t* vw = views ? views + view_off[t] : NULL;
+        int ns = views ? n_sel[t] : g->n_views;
+        orc_grad(g, factor[t], y, b, vw, ns, sigma[t], gr);
+        for (size_t i = 0; i < n; ++i) z[i] = y[i] - eta[t] * gr[i];
+        orc_tv_prox(z, g->nx, g->ny, lambda, tv_iters, tau, x);
+        for (size_t i = 0; i < n; ++i) x[i] = (1.0 - alpha) * z[i] + alpha * x[i];
+        for (size_t i = 0; i < n; ++i) y[i] = x[i] + a[t] * (x[i] - x_prev[i]);
+        if (history) memcpy(history + (size_t)t * n, x, n * sizeof(double));
+        memcpy(x_prev, x, n * sizeof(double));
+    }
+    memcpy(x_out, x_prev, n * sizeof(double));
+    free(x_prev);
+    free(y);
+    free(z);
+    free(x);
+    free(gr);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Lipschitz constant of the sketched data term (step eta = 1/L, Sec. 3)      */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Power iteration on B^T B with B = A_s D_f over all views, from v = 1/sqrt(d):
+ * v <- B^T B v / ||B^T B v||, n_iter times; returns ||B v||^2.
+ */
+double orc_power_lipschitz(const orc_geom* g, int f, int n_iter) {
+    int nx = g->nx, ny = g->ny, nxs = nx / f, nys = ny / f;
+    size_t d = (size_t)nx * ny, ds = (size_t)nxs * nys, ns = (size_t)g->n_views * g->n_bins;
+    double* v = (double*)malloc(d * sizeof(double));
+    double* w = (double*)malloc(d * sizeof(double));
+    double* vs = (double*)malloc(ds * sizeof(double));
+    double* ws = (double*)malloc(ds * sizeof(double));
+    double* s = (double*)malloc(ns * sizeof(double));
+    for (size_t i = 0; i < d; ++i) v[i] = 1.0 / sqrt((double)d);
+    for (int it = 0; it < n_iter; ++it) {
+        orc_down(v, nx, ny, f, vs);
+        orc_fp(g, f, vs, s, NULL, g->n_views);
+        orc_bp(g, f, s, ws, NULL, g->n_views, 1.0);
+        orc_up(ws, nxs, nys, f, w);
+        double nrm = 0.0;
+        for (size_t i = 0; i < d; ++i) nrm += w[i] * w[i];
+        nrm = sqrt(nrm);
+        for (size_t i = 0; i < d; ++i) v[i] = w[i] / nrm;
+    }
+    orc_down(v, nx, ny, f, vs);
+    orc_fp(g, f, vs, s, NULL, g->n_views);
+    double L = 0.0;
+    for (size_t i = 0; i < ns; ++i) L += s[i] * s[i];
+    free(v);
+    free(w);
+    free(vs);
+    free(ws);
+    free(s);
+    return L;
+}
+
+/* Peak signal-to-noise ratio with peak = max(ref) - min(ref), MSE over all pixels. */
+double orc_psnr(const double* x, const double* ref, size_t n) {
+    double lo = ref[0], hi = ref[0], se = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        if (ref[i] < lo) lo = ref[i];
+        if (ref[i] > hi) hi = ref[i];
+        double e = x[i] - ref[i];
+        se += e * e;
+    }
+    double mse = se / (double)n;
+    return 10.0 * log10((hi - lo) * (hi - lo) / mse);
+}
