@@ -1,0 +1,183 @@
+/*
+ * fbpnp: fan-beam CT plug-and-play reconstruction with multi-stage sketched
+ * gradients on AMD MI355X (gfx950).
+ *
+ * Method: Tang, "Accelerating Plug-and-Play Image Reconstruction via
+ * Multi-Stage Sketched Gradients" (arXiv:2203.07308).
+ *   - measurement model b = A x + w ............................ Sec. 1, Eq. (1)
+ *   - least-squares gradient A^T(Ax - b) inside PnP ............. Sec. 2.1, Eq. (5)
+ *   - sketched objective f(b, A_s S(x)), S: R^d -> R^m .......... Sec. 2.1, Eq. (4)
+ *   - sketched gradient U(A_s^T A_s S(x) - A_s^T b) .............. Sec. 2.1, Eq. (6)
+ *   - minibatch (view-subset) gradient with M_k ................. Sec. 2.1, Eq. (7)
+ *   - one PnP-MS2G iteration: sketch, gradient, upsampled step,
+ *     relaxed denoiser, momentum ................................ Sec. 2.1, Algorithm 1
+ *
+ * Conventions (the paper fixes none of them):
+ *   Images are float32, row-major [ny][nx]; row r is the y axis, column c the
+ *   x axis; pixel (r,c) has centre ((c-(nx-1)/2) h, (r-(ny-1)/2) h).
+ *   Sinograms are float32 [views][n_bins], bins contiguous.
+ *   View k has source S = sod (cos b, sin b), b = angle0 + k*angle_step; the
+ *   flat detector is perpendicular to the central ray at distance sdd from the
+ *   source, bin j centred at ((j-(n_bins-1)/2) pitch + det_offset) along
+ *   (-sin b, cos b).
+ *   A is Joseph's ray-driven projector (one ray per bin centre, linear
+ *   interpolation along the minor axis, zero outside the grid). A_s is the same
+ *   projector on the grid coarsened by a pooling factor f (pixel f h), S = D_f
+ *   is f x f average pooling and U = D_f^T (replicate, divide by f^2).
+ *
+ * Memory and threading:
+ *   All array arguments are device pointers (hipMalloc'd or torch tensors) with
+ *   at least 16-byte alignment; the caller owns them. Calls are asynchronous on
+ *   the given stream and never synchronise, allocate or free, except the
+ *   plan/graph create and destroy calls and fb_power_lipschitz (documented).
+ *   A plan owns a device workspace: calls that use one plan must not overlap
+ *   in time (issue them on one stream, or use one plan per stream).
+ *   Outputs never alias inputs unless a call says otherwise.
+ *
+ * Errors: every call returns an fb_status. Arguments are validated on the host
+ * before any launch; on error nothing is launched and fb_last_error() returns
+ * a message (thread-local). No C++ exception crosses this interface. NaN or
+ * Inf values inside arrays are not checked.
+ */
+#ifndef FBPNP_H
+#define FBPNP_H
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int fb_status;
+#define FB_OK 0
+#define FB_EINVAL (-1)  /* null pointer, non-positive size, bad stage or parameter */
+#define FB_EGEOM (-2)   /* geometry not valid (source inside the image circle, fan too wide, non-finite) */
+#define FB_EDIV (-3)    /* image size not divisible by the pooling factor */
+#define FB_ESUBSET (-4) /* view list too long */
+#define FB_EHIP (-5)    /* HIP runtime or launch error (message holds the HIP text) */
+#define FB_ENOMEM (-6)  /* device allocation failed (plan or graph creation only) */
+
+/* Fan-beam geometry of the full-resolution grid. */
+typedef struct fb_geom {
+    int32_t nx, ny;          /* image width (columns) and height (rows) */
+    double pixel_mm;         /* pixel size h */
+    int32_t n_views, n_bins; /* views and detector bins */
+    double sod_mm, sdd_mm;   /* source-to-isocentre, source-to-detector */
+    double det_pitch_mm;     /* bin pitch on the detector */
+    double det_offset_mm;    /* detector shift along (-sin b, cos b) */
+    double angle0_rad, angle_step_rad;
+} fb_geom;
+
+typedef struct fb_plan fb_plan;
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* fb_last_error(void);
+
+/*
+ * Creates a plan for one geometry and n_stages pooling factors (each >= 1,
+ * dividing nx and ny). Stage s is the Joseph projector A_s on the
+ * (ny/f_s) x (nx/f_s) grid with pixel f_s h (Sec. 2.1, Eq. (4)). Ray tables are
+ * computed in double precision on the host and stored in float32 on the
+ * device. Allocates device memory and synchronises the current device.
+ */
+fb_status fb_plan_create(const fb_geom* geom, int n_stages, const int32_t* factors, fb_plan** out);
+fb_status fb_plan_destroy(fb_plan* plan);
+
+/* Stage description: coarse grid, factor, and the number of in-grid Joseph
+ * samples of one projection over all views (the projector's work). */
+typedef struct fb_stage_info {
+    int32_t factor, nxs, nys;
+    int64_t samples_all_views;
+} fb_stage_info;
+fb_status fb_plan_stage_info(const fb_plan* plan, int stage, fb_stage_info* out);
+
+/*
+ * Forward projection y = M A_s x (Sec. 1, Eq. (1); Sec. 2.1, Eq. (4)).
+ *   x: device [nys][nxs] image on the stage's coarse grid.
+ *   views: device int32 list of n_sel view indices (the rows of M), or NULL
+ *     for all views in order (then n_sel must equal n_views).
+ *   y: device [n_sel][n_bins], overwritten.
+ * Uses the plan workspace.
+ */
+fb_status fanbeam_fp(const fb_plan* plan, int stage, const float* x, float* y, const int32_t* views,
+                     int n_sel, hipStream_t stream);
+
+/*
+ * Matched backprojection x = scale * (M A_s)^T y: the exact transpose of
+ * fanbeam_fp (identical interpolation weights), computed as a pixel-driven
+ * gather with no atomics, so results are bitwise reproducible.
+ *   y: device [n_sel][n_bins]; x: device [nys][nxs], overwritten.
+ */
+fb_status fanbeam_bp(const fb_plan* plan, int stage, const float* y, float* x, const int32_t* views,
+                     int n_sel, float scale, hipStream_t stream);
+
+/* Sketch S = D_f: v[R][C] = mean of the f x f block of x (Sec. 2.1, Eq. (4)).
+ * x: device [ny][nx]; v: device [ny/f][nx/f]. */
+fb_status sketch_down(const float* x, int nx, int ny, int f, float* v, hipStream_t stream);
+
+/* Upsampler U = D_f^T: x[r][c] = v[r/f][c/f] / f^2 (Sec. 2.1, Eq. (6)).
+ * v: device [nys][nxs]; x: device [nys*f][nxs*f]. */
+fb_status sketch_up(const float* v, int nxs, int nys, int f, float* x, hipStream_t stream);
+
+/*
+ * Denoiser D (Sec. 2.1, list after Eq. (5)): n_iter steps of Chambolle's dual
+ * projection for isotropic TV with forward differences and Neumann boundary,
+ * from p = 0:  p <- (p + tau grad(div p - z/lambda)) / (1 + tau |grad(.)|),
+ * then x = z - lambda div p. lambda == 0 copies z.
+ *   ws: device workspace of at least fb_tv_workspace_bytes(nx, ny, n_iter)
+ *   bytes (0 bytes, ws may be NULL, when n_iter <= 8).
+ */
+size_t fb_tv_workspace_bytes(int nx, int ny, int n_iter);
+fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_iter, float tau, void* ws,
+                  size_t ws_bytes, hipStream_t stream);
+
+/*
+ * One PnP-MS2G iteration t (Sec. 2.1, Algorithm 1, Option 1 or 2):
+ *   v   = S_k(y_{t-1})                        (pooling of the stage)
+ *   G   = sigma (M A_s)^T (M A_s v - M b)     (minibatch gradient, Eq. (7))
+ *   z   = y_{t-1} - eta U G                   (U = D_f^T)
+ *   x_t = (1 - alpha) z + alpha D(z)          (D: tv_prox with lambda, tau, tv_iters <= 8)
+ *   y_t = x_t + a_t (x_t - x_{t-1})
+ * b is the full sinogram [n_views][n_bins]; views/n_sel select M as in
+ * fanbeam_fp. y_out may equal y_prev and x_out may equal x_prev (in-place
+ * iteration). history, if not NULL, receives a copy of x_t.
+ */
+typedef struct fb_pnp_args {
+    int32_t stage;
+    const int32_t* views;
+    int32_t n_sel;
+    float sigma, eta, alpha, a_t;
+    float lambda, tau;
+    int32_t tv_iters;
+    const float* b;
+    const float* y_prev;
+    const float* x_prev;
+    float* x_out;
+    float* y_out;
+    float* history;
+} fb_pnp_args;
+fb_status pnp_step(const fb_plan* plan, const fb_pnp_args* args, hipStream_t stream);
+
+/*
+ * A whole schedule of pnp_step calls captured once into a HIP graph and
+ * replayed with one launch. The argument arrays are copied at creation; the
+ * device buffers they point to must stay valid while the graph exists.
+ */
+typedef struct fb_graph fb_graph;
+fb_status fb_graph_create(const fb_plan* plan, const fb_pnp_args* steps, int n_steps, fb_graph** out);
+fb_status fb_graph_launch(fb_graph* graph, hipStream_t stream);
+fb_status fb_graph_destroy(fb_graph* graph);
+
+/*
+ * Lipschitz constant L = ||A_s D_f||_2^2 of the stage's data term over all
+ * views (step eta = 1/L, Sec. 3) by n_iter power iterations from the constant
+ * unit vector. Synchronous: blocks until the result is on the host.
+ */
+fb_status fb_power_lipschitz(const fb_plan* plan, int stage, int n_iter, double* out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FBPNP_H */

@@ -1,0 +1,74 @@
+// Internal definitions shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fbpnp.h"
+
+namespace fbpnp {
+
+// Zero padding on both ends of every line of the two line images of a stage.
+constexpr int kPad = 2;
+
+// One ray of one stage: Joseph samples on the major axis lines lo .. lo+n-1.
+// At line lo+k the minor-axis pixel-index coordinate is
+//   pos(k) = npos/2 + fma(k - n/2, dpos, pos_mid)      (integer npos/2, n/2)
+// with npos the number of pixels along the minor axis; ray weight
+// len = f h |d| / |d_major|.
+// bits: lo (16) | n (15) << 16 | axis << 31, axis 0 = x-major (lines are
+// columns, positions are rows), 1 = y-major (lines are rows, positions are
+// columns).
+struct alignas(16) RayRec {
+    float pos_mid, dpos, len;
+    uint32_t bits;
+};
+
+// Per view and stage: the detector coordinate of the ray through pixel-index
+// point (c, r) of the stage grid is
+//   j(c, r) = (a0 + a1 c' + a2 r') / (b0 + b1 c' + b2 r') + j0,
+// with centred indices c' = c - (nxs-1)/2, r' = r - (nys-1)/2, and bins
+// [xlo, xhi] are x-major, [ylo, yhi] y-major (an empty range has lo > hi).
+struct alignas(16) ViewRec {
+    float a0, a1, a2, b0, b1, b2, j0, pad;
+    int32_t xlo, xhi, ylo, yhi;
+};
+
+struct Stage {
+    int f = 1, nxs = 0, nys = 0;
+    int64_t samples = 0;            // in-grid samples over all views
+    RayRec* rays = nullptr;         // device [n_views][n_bins]
+    ViewRec* vrec = nullptr;        // device [n_views]
+    int pitch_x = 0, pitch_y = 0;   // line pitches of the two line images
+};
+
+}  // namespace fbpnp
+
+struct fb_plan {
+    fb_geom g{};
+    std::vector<fbpnp::Stage> stages;
+    int device = 0;
+    // workspace (device)
+    float* line_x = nullptr;   // x-major line image: [nxs][pitch_x], largest stage
+    float* line_y = nullptr;   // y-major line image: [nys][pitch_y]
+    float* resid = nullptr;    // [n_views][n_bins]
+    float* zbuf = nullptr;     // [ny][nx]
+    float* vec = nullptr;      // power iteration: 2 x [ny][nx] + reductions
+    size_t vec_floats = 0;
+};
+
+namespace fbpnp {
+
+// Thread-local error reporting.
+fb_status fail(fb_status code, const std::string& msg);
+fb_status hip_fail(hipError_t e, const char* what);
+
+// Host plan construction (double precision tables), in plan.cpp.
+fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays, std::vector<ViewRec>& views,
+                             int64_t& samples);
+fb_status validate_geometry(const fb_geom& g);
+
+}  // namespace fbpnp

@@ -1,0 +1,172 @@
+// Host side of a projector plan: geometry validation and the per-stage ray and
+// view tables, computed in double precision and stored in float32.
+//
+// Readings of the fan-beam geometry (the paper fixes none): flat detector,
+// one Joseph ray per bin centre, pixel centres at ((c-(nx-1)/2) h, (r-(ny-1)/2) h).
+// Stage grids (pooling factor f, Sec. 2.1 Eq. (4)) keep the same isocentre and
+// use pixel f h.
+#include <cmath>
+#include <cstring>
+
+#include "fbpnp_impl.h"
+
+namespace fbpnp {
+
+static thread_local std::string g_last_error;
+
+fb_status fail(fb_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+fb_status hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return FB_EHIP;
+}
+
+const char* last_error() { return g_last_error.c_str(); }
+
+fb_status validate_geometry(const fb_geom& g) {
+    if (g.nx < 1 || g.ny < 1 || g.n_views < 1 || g.n_bins < 1)
+        return fail(FB_EINVAL, "geometry: nx, ny, n_views and n_bins must be positive");
+    if (g.nx > 32767 || g.ny > 32767) return fail(FB_EINVAL, "geometry: nx and ny must be at most 32767");
+    const double vals[] = {g.pixel_mm, g.sod_mm, g.sdd_mm, g.det_pitch_mm, g.det_offset_mm, g.angle0_rad,
+                           g.angle_step_rad};
+    for (double v : vals)
+        if (!std::isfinite(v)) return fail(FB_EGEOM, "geometry: non-finite parameter");
+    if (g.pixel_mm <= 0 || g.sod_mm <= 0 || g.sdd_mm <= 0 || g.det_pitch_mm <= 0)
+        return fail(FB_EGEOM, "geometry: pixel, sod, sdd and pitch must be positive");
+    double circ = 0.5 * g.pixel_mm * std::sqrt((double)g.nx * g.nx + (double)g.ny * g.ny);
+    if (circ >= g.sod_mm) return fail(FB_EGEOM, "geometry: source inside the image circumcircle");
+    double umax = std::fabs(0.5 * (g.n_bins - 1) * g.det_pitch_mm) + std::fabs(g.det_offset_mm);
+    if (umax >= g.sdd_mm) return fail(FB_EGEOM, "geometry: fan wider than 90 degrees");
+    return FB_OK;
+}
+
+// Index range [lo, hi] of lines l in [0, nlines) with pos(l) = p0 + l*dp in (-1, npos).
+static void valid_range(double p0, double dp, int nlines, int npos, int& lo, int& hi) {
+    auto ok = [&](int l) {
+        double p = p0 + (double)l * dp;
+        return p > -1.0 && p < (double)npos;
+    };
+    if (dp == 0.0) {
+        if (ok(0)) {
+            lo = 0;
+            hi = nlines - 1;
+        } else {
+            lo = 0;
+            hi = -1;
+        }
+        return;
+    }
+    double a = (-1.0 - p0) / dp, b = ((double)npos - p0) / dp;
+    if (a > b) std::swap(a, b);
+    double flo = std::floor(a) + 1.0, fhi = std::ceil(b) - 1.0;
+    flo = std::max(flo, 0.0);
+    fhi = std::min(fhi, (double)(nlines - 1));
+    if (flo > fhi) {
+        lo = 0;
+        hi = -1;
+        return;
+    }
+    lo = (int)flo;
+    hi = (int)fhi;
+    while (lo <= hi && !ok(lo)) ++lo;
+    while (hi >= lo && !ok(hi)) --hi;
+    if (lo > hi) {
+        lo = 0;
+        hi = -1;
+        return;
+    }
+    while (lo > 0 && ok(lo - 1)) --lo;
+    while (hi < nlines - 1 && ok(hi + 1)) ++hi;
+}
+
+fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays, std::vector<ViewRec>& views,
+                             int64_t& samples) {
+    const int nxs = g.nx / f, nys = g.ny / f, nb = g.n_bins;
+    const double hs = g.pixel_mm * f;
+    const double cxs = 0.5 * (nxs - 1), cys = 0.5 * (nys - 1);
+    rays.assign((size_t)g.n_views * nb, RayRec{0.f, 0.f, 0.f, 0u});
+    views.assign(g.n_views, ViewRec{});
+    samples = 0;
+    for (int k = 0; k < g.n_views; ++k) {
+        const double beta = g.angle0_rad + (double)k * g.angle_step_rad;
+        const double cb = std::cos(beta), sb = std::sin(beta);
+        const double sx = g.sod_mm * cb, sy = g.sod_mm * sb;
+        const double cx = (g.sod_mm - g.sdd_mm) * cb, cy = (g.sod_mm - g.sdd_mm) * sb;
+        int xlo = nb, xhi = -1, ylo = nb, yhi = -1;
+        for (int j = 0; j < nb; ++j) {
+            const double u = ((double)j - 0.5 * (nb - 1)) * g.det_pitch_mm + g.det_offset_mm;
+            const double dx = cx - u * sb - sx, dy = cy + u * cb - sy;
+            const double len = std::sqrt(dx * dx + dy * dy);
+            const bool xmajor = std::fabs(dx) >= std::fabs(dy);
+            double p0, dp, w;
+            int nlines, npos;
+            if (xmajor) {
+                // row coordinate where the ray crosses the centre of column c,
+                // rows per column dp (square pixels)
+                dp = dy / dx;
+                p0 = (sy + (-cxs * hs - sx) * dp) / hs + cys;
+                w = hs * len / std::fabs(dx);
+                nlines = nxs;
+                npos = nys;
+                xlo = std::min(xlo, j);
+                xhi = std::max(xhi, j);
+            } else {
+                dp = dx / dy;
+                p0 = (sx + (-cys * hs - sy) * dp) / hs + cxs;
+                w = hs * len / std::fabs(dy);
+                nlines = nys;
+                npos = nxs;
+                ylo = std::min(ylo, j);
+                yhi = std::max(yhi, j);
+            }
+            int lo, hi;
+            valid_range(p0, dp, nlines, npos, lo, hi);
+            RayRec& r = rays[(size_t)k * nb + j];
+            if (hi >= lo) {
+                const int n = hi - lo + 1;
+                // reference sample k = n/2, position relative to the integer npos/2:
+                // both keep the float magnitudes (and rounding) small
+                r.pos_mid = (float)(p0 + (double)(lo + n / 2) * dp - (double)(npos / 2));
+                r.dpos = (float)dp;
+                r.len = (float)w;
+                r.bits = (uint32_t)lo | ((uint32_t)n << 16) | (xmajor ? 0u : 0x80000000u);
+                samples += n;
+            } else {
+                r.pos_mid = 0.f;
+                r.dpos = 0.f;
+                r.len = (float)w;
+                r.bits = xmajor ? 0u : 0x80000000u;
+            }
+        }
+        // each dominance class must be one contiguous bin range
+        for (int j = 0; j < nb; ++j) {
+            const bool ym = rays[(size_t)k * nb + j].bits >> 31;
+            if (!ym && (j < xlo || j > xhi)) return fail(FB_EGEOM, "geometry: x-major bins not contiguous");
+            if (ym && (j < ylo || j > yhi)) return fail(FB_EGEOM, "geometry: y-major bins not contiguous");
+            if (!ym && j >= ylo && j <= yhi) return fail(FB_EGEOM, "geometry: dominance classes interleave");
+        }
+        // detector coordinate of the ray through stage pixel (c, r), centred indices
+        const double K = g.sdd_mm / g.det_pitch_mm / g.sod_mm;
+        ViewRec& v = views[k];
+        v.a0 = 0.f;
+        v.a1 = (float)(-K * hs * sb);
+        v.a2 = (float)(K * hs * cb);
+        v.b0 = 1.f;
+        v.b1 = (float)(-hs * cb / g.sod_mm);
+        v.b2 = (float)(-hs * sb / g.sod_mm);
+        v.j0 = (float)(0.5 * (nb - 1) - g.det_offset_mm / g.det_pitch_mm);
+        v.pad = 0.f;
+        v.xlo = xlo;
+        v.xhi = xhi;
+        v.ylo = ylo;
+        v.yhi = yhi;
+    }
+    return FB_OK;
+}
+
+}  // namespace fbpnp
+
+extern "C" const char* fb_last_error(void) { return fbpnp::last_error(); }

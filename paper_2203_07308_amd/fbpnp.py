@@ -1,0 +1,277 @@
+"""Thin ctypes binding of libfbpnp (include/fbpnp.h) for torch tensors.
+
+Argument marshalling only: every array must be a contiguous float32 (or int32 for
+view lists) tensor on the GPU; the call is enqueued on torch's current stream. All
+arithmetic runs in the library's HIP kernels. There is no CPU fallback: a missing
+library or a failing call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfbpnp.so")
+
+FB_OK = 0
+_STATUS = {-1: "FB_EINVAL", -2: "FB_EGEOM", -3: "FB_EDIV", -4: "FB_ESUBSET", -5: "FB_EHIP", -6: "FB_ENOMEM"}
+
+# every exported entry point, in the order of include/fbpnp.h
+EXPORTS = [
+    "fb_last_error", "fb_plan_create", "fb_plan_destroy", "fb_plan_stage_info", "fanbeam_fp", "fanbeam_bp",
+    "sketch_down", "sketch_up", "fb_tv_workspace_bytes", "tv_prox", "pnp_step", "fb_graph_create",
+    "fb_graph_launch", "fb_graph_destroy", "fb_power_lipschitz",
+]
+
+
+class FbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("pixel_mm", ctypes.c_double),
+        ("n_views", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+        ("sod_mm", ctypes.c_double), ("sdd_mm", ctypes.c_double),
+        ("det_pitch_mm", ctypes.c_double), ("det_offset_mm", ctypes.c_double),
+        ("angle0_rad", ctypes.c_double), ("angle_step_rad", ctypes.c_double),
+    ]
+
+
+class StageInfo(ctypes.Structure):
+    _fields_ = [("factor", ctypes.c_int32), ("nxs", ctypes.c_int32), ("nys", ctypes.c_int32),
+                ("samples_all_views", ctypes.c_int64)]
+
+
+class PnpArgs(ctypes.Structure):
+    _fields_ = [
+        ("stage", ctypes.c_int32), ("views", ctypes.c_void_p), ("n_sel", ctypes.c_int32),
+        ("sigma", ctypes.c_float), ("eta", ctypes.c_float), ("alpha", ctypes.c_float), ("a_t", ctypes.c_float),
+        ("lambda_", ctypes.c_float), ("tau", ctypes.c_float), ("tv_iters", ctypes.c_int32),
+        ("b", ctypes.c_void_p), ("y_prev", ctypes.c_void_p), ("x_prev", ctypes.c_void_p),
+        ("x_out", ctypes.c_void_p), ("y_out", ctypes.c_void_p), ("history", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libfbpnp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2203_07308_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_float, vp = ctypes.c_int, ctypes.c_float, ctypes.c_void_p
+    P = ctypes.POINTER
+    lib.fb_last_error.restype = ctypes.c_char_p
+    lib.fb_last_error.argtypes = []
+    lib.fb_plan_create.argtypes = [P(Geom), c_int, P(ctypes.c_int32), P(vp)]
+    lib.fb_plan_destroy.argtypes = [vp]
+    lib.fb_plan_stage_info.argtypes = [vp, c_int, P(StageInfo)]
+    lib.fanbeam_fp.argtypes = [vp, c_int, vp, vp, vp, c_int, vp]
+    lib.fanbeam_bp.argtypes = [vp, c_int, vp, vp, vp, c_int, c_float, vp]
+    lib.sketch_down.argtypes = [vp, c_int, c_int, c_int, vp, vp]
+    lib.sketch_up.argtypes = [vp, c_int, c_int, c_int, vp, vp]
+    lib.fb_tv_workspace_bytes.argtypes = [c_int, c_int, c_int]
+    lib.fb_tv_workspace_bytes.restype = ctypes.c_size_t
+    lib.tv_prox.argtypes = [vp, vp, c_int, c_int, c_float, c_int, c_float, vp, ctypes.c_size_t, vp]
+    lib.pnp_step.argtypes = [vp, P(PnpArgs), vp]
+    lib.fb_graph_create.argtypes = [vp, P(PnpArgs), c_int, P(vp)]
+    lib.fb_graph_launch.argtypes = [vp, vp]
+    lib.fb_graph_destroy.argtypes = [vp]
+    lib.fb_power_lipschitz.argtypes = [vp, c_int, c_int, P(ctypes.c_double), vp]
+    for name in EXPORTS:
+        if name not in ("fb_last_error", "fb_tv_workspace_bytes"):
+            getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != FB_OK:
+        raise FbError(status, load().fb_last_error().decode())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None, dtype=torch.float32, numel: int | None = None, name: str = "tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass(frozen=True)
+class Geometry:
+    nx: int
+    ny: int
+    pixel_mm: float
+    n_views: int
+    n_bins: int
+    sod_mm: float
+    sdd_mm: float
+    det_pitch_mm: float
+    det_offset_mm: float = 0.0
+    angle0_rad: float = 0.0
+    angle_step_rad: float | None = None
+
+    def c(self) -> Geom:
+        import math
+
+        step = self.angle_step_rad if self.angle_step_rad is not None else 2 * math.pi / max(self.n_views, 1)
+        return Geom(self.nx, self.ny, self.pixel_mm, self.n_views, self.n_bins, self.sod_mm, self.sdd_mm,
+                    self.det_pitch_mm, self.det_offset_mm, self.angle0_rad, step)
+
+
+class Plan:
+    """Projector plan (fb_plan_create): one geometry, one stage per pooling factor."""
+
+    def __init__(self, geom: Geometry, factors=(1,)):
+        lib = load()
+        self.geom = geom
+        self.factors = [int(f) for f in factors]
+        arr = (ctypes.c_int32 * len(self.factors))(*self.factors)
+        h = ctypes.c_void_p()
+        _check(lib.fb_plan_create(ctypes.byref(geom.c()), len(self.factors), arr, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().fb_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stage_info(self, stage: int) -> StageInfo:
+        out = StageInfo()
+        _check(load().fb_plan_stage_info(self._h, stage, ctypes.byref(out)))
+        return out
+
+    def coarse_shape(self, stage: int):
+        f = self.factors[stage]
+        return (self.geom.ny // f, self.geom.nx // f)
+
+
+def _views(plan: Plan, views: torch.Tensor | None):
+    if views is None:
+        return None, plan.geom.n_views
+    return _ptr(views, torch.int32, name="views"), views.numel()
+
+
+def fanbeam_fp(plan: Plan, stage: int, x: torch.Tensor, y: torch.Tensor, views: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    ny, nx = plan.coarse_shape(stage)
+    vp, n_sel = _views(plan, views)
+    _check(load().fanbeam_fp(plan.handle, stage, _ptr(x, numel=nx * ny, name="x"),
+                             _ptr(y, numel=n_sel * plan.geom.n_bins, name="y"), vp, n_sel, _stream(stream)))
+    return y
+
+
+def fanbeam_bp(plan: Plan, stage: int, y: torch.Tensor, x: torch.Tensor, views: torch.Tensor | None = None,
+               scale: float = 1.0, stream=None) -> torch.Tensor:
+    ny, nx = plan.coarse_shape(stage)
+    vp, n_sel = _views(plan, views)
+    _check(load().fanbeam_bp(plan.handle, stage, _ptr(y, numel=n_sel * plan.geom.n_bins, name="y"),
+                             _ptr(x, numel=nx * ny, name="x"), vp, n_sel, float(scale), _stream(stream)))
+    return x
+
+
+def sketch_down(x: torch.Tensor, f: int, v: torch.Tensor, stream=None) -> torch.Tensor:
+    ny, nx = x.shape
+    _check(load().sketch_down(_ptr(x, name="x"), nx, ny, f, _ptr(v, numel=(nx // f) * (ny // f), name="v"),
+                              _stream(stream)))
+    return v
+
+
+def sketch_up(v: torch.Tensor, f: int, x: torch.Tensor, stream=None) -> torch.Tensor:
+    nys, nxs = v.shape
+    _check(load().sketch_up(_ptr(v, name="v"), nxs, nys, f, _ptr(x, numel=nxs * nys * f * f, name="x"),
+                            _stream(stream)))
+    return x
+
+
+def tv_workspace_bytes(nx: int, ny: int, n_iter: int) -> int:
+    return int(load().fb_tv_workspace_bytes(nx, ny, n_iter))
+
+
+def tv_prox(z: torch.Tensor, x: torch.Tensor, lam: float, n_iter: int = 5, tau: float = 0.125,
+            ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    ny, nx = z.shape
+    need = tv_workspace_bytes(nx, ny, n_iter)
+    if need and ws is None:
+        ws = torch.empty(need // 4, dtype=torch.float32, device=z.device)
+    wsb = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(load().tv_prox(_ptr(z, name="z"), _ptr(x, numel=nx * ny, name="x"), nx, ny, float(lam), int(n_iter),
+                          float(tau), None if ws is None else ctypes.c_void_p(ws.data_ptr()), wsb, _stream(stream)))
+    return x
+
+
+def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float, a_t: float,
+             views: torch.Tensor | None = None, sigma: float = 1.0, alpha: float = 1.0, lam: float = 0.01,
+             tau: float = 0.125, tv_iters: int = 5, history: torch.Tensor | None = None) -> PnpArgs:
+    npix = plan.geom.nx * plan.geom.ny
+    vp, n_sel = _views(plan, views)
+    return PnpArgs(stage, vp, n_sel, sigma, eta, alpha, a_t, lam, tau, tv_iters,
+                   _ptr(b, numel=plan.geom.n_views * plan.geom.n_bins, name="b"),
+                   _ptr(y_prev, numel=npix, name="y_prev"), _ptr(x_prev, numel=npix, name="x_prev"),
+                   _ptr(x_out, numel=npix, name="x_out"), _ptr(y_out, numel=npix, name="y_out"),
+                   _ptr(history, numel=npix, name="history"))
+
+
+def pnp_step(plan: Plan, args: PnpArgs, stream=None) -> None:
+    _check(load().pnp_step(plan.handle, ctypes.byref(args), _stream(stream)))
+
+
+class Graph:
+    """A schedule of pnp_step calls captured into one HIP graph (fb_graph_create)."""
+
+    def __init__(self, plan: Plan, steps):
+        arr = (PnpArgs * len(steps))(*steps)
+        h = ctypes.c_void_p()
+        _check(load().fb_graph_create(plan.handle, arr, len(steps), ctypes.byref(h)))
+        self._h = h
+        self._plan = plan  # keep the plan alive
+
+    def launch(self, stream=None):
+        _check(load().fb_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().fb_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def power_lipschitz(plan: Plan, stage: int, n_iter: int = 100, stream=None) -> float:
+    out = ctypes.c_double()
+    _check(load().fb_power_lipschitz(plan.handle, stage, n_iter, ctypes.byref(out), _stream(stream)))
+    return out.value
