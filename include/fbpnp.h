@@ -97,7 +97,9 @@ fb_status fb_plan_stage_info(const fb_plan* plan, int stage, fb_stage_info* out)
  * Forward projection y = M A_s x (Sec. 1, Eq. (1); Sec. 2.1, Eq. (4)).
  *   x: device [nys][nxs] image on the stage's coarse grid.
  *   views: device int32 list of n_sel view indices (the rows of M), or NULL
- *     for all views in order (then n_sel must equal n_views).
+ *     for all views in order (then n_sel must equal n_views). Repeats are
+ *     allowed; an index outside [0, n_views) yields a zero row (fp) or no
+ *     contribution (bp); indices are not checked on the host.
  *   y: device [n_sel][n_bins], overwritten.
  * Uses the plan workspace.
  */

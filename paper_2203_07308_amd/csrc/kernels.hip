@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_prepare(const float* __restrict__ x, in
 // ---------------------------------------------------------------------------
 template <bool kResid>
 __global__ __launch_bounds__(256) void k_fp(const RayRec* __restrict__ rays, int n_bins, int bins_padded,
-                                            const int32_t* __restrict__ views, int n_sel,
+                                            const int32_t* __restrict__ views, int n_sel, int n_views,
                                             const float* __restrict__ lx, int pitch_x,
                                             const float* __restrict__ ly, int pitch_y, int nxs, int nys,
                                             const float* __restrict__ b, float* __restrict__ y) {
@@ -87,6 +87,10 @@ __global__ __launch_bounds__(256) void k_fp(const RayRec* __restrict__ rays, int
     const int j = t - i * bins_padded;
     if (i >= n_sel || j >= n_bins) return;
     const int v = views ? views[i] : i;
+    if ((unsigned)v >= (unsigned)n_views) {  // invalid view index: a zero row
+        y[(size_t)i * n_bins + j] = 0.f;
+        return;
+    }
     const RayRec r = rays[(size_t)v * n_bins + j];
     const uint32_t lo = r.bits & 0xFFFFu, n = (r.bits >> 16) & 0x7FFFu;
     const bool ymaj = (r.bits >> 31) != 0u;
@@ -169,7 +173,8 @@ __device__ __forceinline__ void cand_range(float j1, float j2, int lo, int hi, i
 template <int VG, bool kFused>
 __global__ __launch_bounds__(64 * VG) void k_bp(const RayRec* __restrict__ rays, const ViewRec* __restrict__ vrec,
                                                 int n_bins, const int32_t* __restrict__ views, int n_sel,
-                                                const float* __restrict__ y, int nxs, int nys, int blocks_x,
+                                                int n_views, const float* __restrict__ y, int nxs, int nys,
+                                                int blocks_x,
                                                 float scale, float* __restrict__ xo, int f, int nx,
                                                 const float* __restrict__ yprev, float* __restrict__ z) {
     __shared__ float red[VG > 1 ? VG - 1 : 1][4][64];
@@ -180,6 +185,7 @@ __global__ __launch_bounds__(64 * VG) void k_bp(const RayRec* __restrict__ rays,
     float a00 = 0.f, a01 = 0.f, a10 = 0.f, a11 = 0.f;  // (r,c) (r,c+1) (r+1,c) (r+1,c+1)
     for (int i = wave; i < n_sel; i += VG) {
         const int v = __builtin_amdgcn_readfirstlane(views ? views[i] : i);
+        if ((unsigned)v >= (unsigned)n_views) continue;  // invalid view index: no contribution
         const ViewRec vr = vrec[v];
         const RayRec* rv = rays + (size_t)v * n_bins;
         const float* yv = y + (size_t)i * n_bins;
@@ -440,10 +446,10 @@ fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* view
     const int nb = p->g.n_bins, bp = cdiv(nb, 64) * 64;
     const int blocks = cdiv(n_sel * bp, 256);
     if (resid)
-        k_fp<true><<<blocks, 256, 0, s>>>(st.rays, nb, bp, views, n_sel, L.lx, st.pitch_x, L.ly, st.pitch_y, st.nxs,
+        k_fp<true><<<blocks, 256, 0, s>>>(st.rays, nb, bp, views, n_sel, p->g.n_views, L.lx, st.pitch_x, L.ly, st.pitch_y, st.nxs,
                                           st.nys, b, y);
     else
-        k_fp<false><<<blocks, 256, 0, s>>>(st.rays, nb, bp, views, n_sel, L.lx, st.pitch_x, L.ly, st.pitch_y,
+        k_fp<false><<<blocks, 256, 0, s>>>(st.rays, nb, bp, views, n_sel, p->g.n_views, L.lx, st.pitch_x, L.ly, st.pitch_y,
                                            st.nxs, st.nys, b, y);
     return check_launch("fanbeam_fp");
 }
@@ -457,7 +463,8 @@ fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const int32_t
     while (vg < 16 && nblk * vg < 2048 && vg * 2 <= n_sel) vg *= 2;
     const int nb = p->g.n_bins, f = st.f, nx = p->g.nx;
 #define FB_BP(VG)                                                                                           \
-    k_bp<VG, kFused><<<nblk, 64 * VG, 0, s>>>(st.rays, st.vrec, nb, views, n_sel, y, st.nxs, st.nys, bxs, scale, \
+    k_bp<VG, kFused><<<nblk, 64 * VG, 0, s>>>(st.rays, st.vrec, nb, views, n_sel, p->g.n_views, y, st.nxs,      \
+                                              st.nys, bxs, scale,                                              \
                                               xo, f, nx, yprev, z)
     switch (vg) {
         case 1: FB_BP(1); break;
