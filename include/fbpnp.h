@@ -145,6 +145,11 @@ fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_
  * b is the full sinogram [n_views][n_bins]; views/n_sel select M as in
  * fanbeam_fp. y_out may equal y_prev and x_out may equal x_prev (in-place
  * iteration). history, if not NULL, receives a copy of x_t.
+ * Chaining (optional, set automatically by fb_graph_create): next_stage >= 0
+ * makes this call also pool y_t for stage next_stage into the plan workspace;
+ * the next call may then set prepared = 1 to skip its own pooling, which is
+ * valid only if it uses that stage and its y_prev is this call's y_out. Use
+ * next_stage = -1 and prepared = 0 for independent calls.
  */
 typedef struct fb_pnp_args {
     int32_t stage;
@@ -159,6 +164,8 @@ typedef struct fb_pnp_args {
     float* x_out;
     float* y_out;
     float* history;
+    int32_t next_stage;
+    int32_t prepared;
 } fb_pnp_args;
 fb_status pnp_step(const fb_plan* plan, const fb_pnp_args* args, hipStream_t stream);
 

@@ -94,6 +94,8 @@ def _load():
         lib.orc_power_lipschitz.restype = d
         lib.orc_psnr.argtypes = [dp, dp, ctypes.c_size_t]
         lib.orc_psnr.restype = d
+        lib.orc_tv_relax_vjp.argtypes = [dp, dp, i32, i32, d, i32, d, d, dp]
+        lib.orc_pnp_vjp.argtypes = [gp, i32, ip, ip, ip, ip, dp, dp, dp, d, d, i32, d, dp, dp, dp, dp, dp]
         _lib = lib
     return _lib
 
@@ -224,6 +226,44 @@ def pnp_run(g: Geometry, b, schedule, eta, a, alpha: float = 1.0, lam: float = 0
                         _dp(eta), _dp(a), alpha, lam, tv_iters, tau, _dp(b), _dp(x0), _dp(xo),
                         _dp(hist) if history else None)
     return (xo, hist) if history else xo
+
+
+def tv_relax_vjp(z, xbar, lam: float, n_iter: int = 5, tau: float = 0.125, alpha: float = 1.0) -> np.ndarray:
+    """Vector-Jacobian product of z -> (1 - alpha) z + alpha TV_prox(z) (reverse mode of
+    the relaxed denoiser step of Algorithm 1)."""
+    z, xbar = _f64(z), _f64(xbar)
+    ny, nx = z.shape
+    out = np.zeros_like(z)
+    _load().orc_tv_relax_vjp(_dp(z), _dp(xbar), nx, ny, lam, n_iter, tau, alpha, _dp(out))
+    return out
+
+
+def _schedule_arrays(g: Geometry, schedule):
+    factor = np.array([s[0] for s in schedule], dtype=np.int32)
+    sigma = _f64([s[2] for s in schedule])
+    lists = [np.arange(g.n_views, dtype=np.int32) if s[1] is None else np.asarray(s[1], np.int32)
+             for s in schedule]
+    n_sel = np.array([len(l) for l in lists], dtype=np.int32)
+    off = np.concatenate([[0], np.cumsum(n_sel)[:-1]]).astype(np.int32)
+    views = np.ascontiguousarray(np.concatenate(lists), dtype=np.int32)
+    return factor, sigma, views, off, n_sel
+
+
+def pnp_vjp(g: Geometry, b, schedule, eta, a, xT_bar, alpha: float = 1.0, lam: float = 0.01,
+            tv_iters: int = 5, tau: float = 0.125, x0=None):
+    """Reverse mode of pnp_run: given dL/dx_T, returns (dL/dx_0, dL/deta_t for t = 1..T)."""
+    T = len(schedule)
+    factor, sigma, views, off, n_sel = _schedule_arrays(g, schedule)
+    eta, a, b = _f64(eta), _f64(a), _f64(b)
+    x0 = np.zeros((g.ny, g.nx)) if x0 is None else _f64(x0)
+    xT_bar = _f64(xT_bar)
+    x0_bar = np.zeros((g.ny, g.nx))
+    eta_bar = np.zeros(T)
+    ip = lambda arr: arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+    _load().orc_pnp_vjp(ctypes.byref(g.c()), T, ip(factor), ip(views), ip(off), ip(n_sel), _dp(sigma), _dp(eta),
+                        _dp(a), alpha, lam, tv_iters, tau, _dp(b), _dp(x0), _dp(xT_bar), _dp(x0_bar),
+                        _dp(eta_bar))
+    return x0_bar, eta_bar
 
 
 def power_lipschitz(g: Geometry, f: int = 1, n_iter: int = 100) -> float:

@@ -466,3 +466,178 @@ double orc_psnr(const double* x, const double* ref, size_t n) {
     double mse = se / (double)n;
     return 10.0 * log10((hi - lo) * (hi - lo) / mse);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Reverse mode (differentiation of the unrolled iteration)                  */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * zbar = J^T xbar for x = alpha_tv * (TV(z) - z) + z, i.e. the vector-Jacobian
+ * product of the relaxed denoiser z -> (1 - alpha) z + alpha TV(z) with the
+ * identity part kept at weight 1 (alpha_tv = alpha). The dual iterates p^n,
+ * u^n = div p^n - z/lambda and q^n = grad u^n are recomputed, then the steps
+ *   p^{n+1} = (p^n + tau q^n) / (1 + tau |q^n|),  x = z - lambda div p^K
+ * are reversed. d|q|/dq is taken as 0 at q = 0.
+ */
+void orc_tv_relax_vjp(const double* z, const double* xbar, int nx, int ny, double lambda, int n_iter,
+                      double tau, double alpha, double* zbar) {
+    size_t n = (size_t)nx * ny;
+    if (lambda == 0.0 || n_iter == 0) {
+        memcpy(zbar, xbar, n * sizeof(double));
+        return;
+    }
+    int K = n_iter;
+    double* P1 = (double*)calloc(n * (K + 1), sizeof(double)); /* p^0..p^K, row part */
+    double* P2 = (double*)calloc(n * (K + 1), sizeof(double)); /* column part */
+    double* U = (double*)malloc(n * K * sizeof(double));
+    double* dv = (double*)malloc(n * sizeof(double));
+    for (int it = 0; it < K; ++it) {
+        double *p1 = P1 + it * n, *p2 = P2 + it * n, *u = U + it * n;
+        tv_div(p1, p2, nx, ny, dv);
+        for (size_t i = 0; i < n; ++i) u[i] = dv[i] - z[i] / lambda;
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)r * nx + c;
+                double q1 = (r < ny - 1) ? u[i + nx] - u[i] : 0.0;
+                double q2 = (c < nx - 1) ? u[i + 1] - u[i] : 0.0;
+                double den = 1.0 + tau * sqrt(q1 * q1 + q2 * q2);
+                P1[(it + 1) * n + i] = (p1[i] + tau * q1) / den;
+                P2[(it + 1) * n + i] = (p2[i] + tau * q2) / den;
+            }
+    }
+    /* x = z - lambda div p^K, weighted by alpha on the denoiser path */
+    double* pb1 = (double*)malloc(n * sizeof(double));
+    double* pb2 = (double*)malloc(n * sizeof(double));
+    double* qb1 = (double*)malloc(n * sizeof(double));
+    double* qb2 = (double*)malloc(n * sizeof(double));
+    double* ub = (double*)malloc(n * sizeof(double));
+    memcpy(zbar, xbar, n * sizeof(double));
+    /* adjoint of div: (div^T w)_1[r,c] = [r<ny-1](w[r,c] - w[r+1,c]), likewise columns */
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            size_t i = (size_t)r * nx + c;
+            double w = -lambda * alpha * xbar[i];
+            pb1[i] = (r < ny - 1) ? w - (-lambda * alpha * xbar[i + nx]) : 0.0;
+            pb2[i] = (c < nx - 1) ? w - (-lambda * alpha * xbar[i + 1]) : 0.0;
+        }
+    for (int it = K - 1; it >= 0; --it) {
+        const double* u = U + it * n;
+        const double *pn1 = P1 + (it + 1) * n, *pn2 = P2 + (it + 1) * n;
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)r * nx + c;
+                double q1 = (r < ny - 1) ? u[i + nx] - u[i] : 0.0;
+                double q2 = (c < nx - 1) ? u[i + 1] - u[i] : 0.0;
+                double mag = sqrt(q1 * q1 + q2 * q2);
+                double den = 1.0 + tau * mag;
+                double nb1 = pb1[i] / den, nb2 = pb2[i] / den;
+                double db = -(pb1[i] * pn1[i] + pb2[i] * pn2[i]) / den;
+                double magb = tau * db;
+                qb1[i] = tau * nb1 + (mag > 0.0 ? magb * q1 / mag : 0.0);
+                qb2[i] = tau * nb2 + (mag > 0.0 ? magb * q2 / mag : 0.0);
+                pb1[i] = nb1;
+                pb2[i] = nb2;
+            }
+        /* q = masked forward differences of u: u_bar = transpose applied to q_bar */
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)r * nx + c;
+                double s = 0.0;
+                if (r < ny - 1) s -= qb1[i];
+                if (r > 0) s += qb1[i - nx];
+                if (c < nx - 1) s -= qb2[i];
+                if (c > 0) s += qb2[i - 1];
+                ub[i] = s;
+            }
+        /* u = div p^n - z / lambda */
+        for (int r = 0; r < ny; ++r)
+            for (int c = 0; c < nx; ++c) {
+                size_t i = (size_t)r * nx + c;
+                if (r < ny - 1) pb1[i] += ub[i] - ub[i + nx];
+                if (c < nx - 1) pb2[i] += ub[i] - ub[i + 1];
+                zbar[i] -= ub[i] / lambda;
+            }
+    }
+    free(P1);
+    free(P2);
+    free(U);
+    free(dv);
+    free(pb1);
+    free(pb2);
+    free(qb1);
+    free(qb2);
+    free(ub);
+}
+
+/*
+ * Gradient of L(x_T) through T iterations of the loop of orc_pnp_run, given
+ * xT_bar = dL/dx_T (y_T does not enter L). Outputs dL/dx_0 (with x_0 = y_0) and
+ * dL/deta_t for every t. Each iteration's inputs (x_{t-1}, y_{t-1}) are kept;
+ * its gradient and z are recomputed on the way back. With
+ *   z = y - eta G(y),  G(y) = sigma U (M A_s)^T (M A_s S y - M b)  (affine, with
+ *   symmetric linear part H = sigma U (M A_s)^T M A_s S),
+ *   x_t = (1 - alpha) z + alpha D(z),  y_t = x_t + a_t (x_t - x_{t-1}):
+ *   xbar_t += (1 + a_t) ybar_t;  xbar_{t-1} = -a_t ybar_t;
+ *   zbar = J_relax^T xbar_t;  eta_bar_t = -<zbar, G(y_{t-1})>;
+ *   ybar_{t-1} = zbar - eta_t H zbar.
+ */
+void orc_pnp_vjp(const orc_geom* g, int T, const int32_t* factor, const int32_t* views,
+                 const int32_t* view_off, const int32_t* n_sel, const double* sigma, const double* eta,
+                 const double* a, double alpha, double lambda, int tv_iters, double tau, const double* b,
+                 const double* x0, const double* xT_bar, double* x0_bar, double* eta_bar) {
+    size_t n = (size_t)g->nx * g->ny, nb = (size_t)g->n_views * g->n_bins;
+    double* X = (double*)malloc(n * (T + 1) * sizeof(double)); /* x_0..x_T */
+    double* Y = (double*)malloc(n * (T + 1) * sizeof(double)); /* y_0..y_T */
+    double* gr = (double*)malloc(n * sizeof(double));
+    double* z = (double*)malloc(n * sizeof(double));
+    double* x = (double*)malloc(n * sizeof(double));
+    double* zero_b = (double*)calloc(nb, sizeof(double));
+    memcpy(X, x0, n * sizeof(double));
+    memcpy(Y, x0, n * sizeof(double));
+    for (int t = 0; t < T; ++t) {
+        const int32_t* vw = views ? views + view_off[t] : NULL;
+        int ns = views ? n_sel[t] : g->n_views;
+        const double* y = Y + t * n;
+        orc_grad(g, factor[t], y, b, vw, ns, sigma[t], gr);
+        for (size_t i = 0; i < n; ++i) z[i] = y[i] - eta[t] * gr[i];
+        orc_tv_prox(z, g->nx, g->ny, lambda, tv_iters, tau, x);
+        double* xt = X + (t + 1) * n;
+        double* yt = Y + (t + 1) * n;
+        for (size_t i = 0; i < n; ++i) xt[i] = (1.0 - alpha) * z[i] + alpha * x[i];
+        for (size_t i = 0; i < n; ++i) yt[i] = xt[i] + a[t] * (xt[i] - X[t * n + i]);
+    }
+    double* xb = (double*)malloc(n * sizeof(double));
+    double* yb = (double*)calloc(n, sizeof(double));
+    double* zb = (double*)malloc(n * sizeof(double));
+    double* hz = (double*)malloc(n * sizeof(double));
+    memcpy(xb, xT_bar, n * sizeof(double));
+    for (int t = T - 1; t >= 0; --t) {
+        const int32_t* vw = views ? views + view_off[t] : NULL;
+        int ns = views ? n_sel[t] : g->n_views;
+        const double* y = Y + t * n;
+        orc_grad(g, factor[t], y, b, vw, ns, sigma[t], gr);
+        for (size_t i = 0; i < n; ++i) z[i] = y[i] - eta[t] * gr[i];
+        for (size_t i = 0; i < n; ++i) xb[i] += (1.0 + a[t]) * yb[i];
+        orc_tv_relax_vjp(z, xb, g->nx, g->ny, lambda, tv_iters, tau, alpha, zb);
+        double e = 0.0;
+        for (size_t i = 0; i < n; ++i) e += zb[i] * gr[i];
+        eta_bar[t] = -e;
+        orc_grad(g, factor[t], zb, zero_b, vw, ns, sigma[t], hz); /* H zbar */
+        for (size_t i = 0; i < n; ++i) {
+            double ynew = zb[i] - eta[t] * hz[i];
+            xb[i] = -a[t] * yb[i];
+            yb[i] = ynew;
+        }
+    }
+    for (size_t i = 0; i < n; ++i) x0_bar[i] = xb[i] + yb[i];
+    free(X);
+    free(Y);
+    free(gr);
+    free(z);
+    free(x);
+    free(zero_b);
+    free(xb);
+    free(yb);
+    free(zb);
+    free(hz);
+}

@@ -14,16 +14,18 @@ namespace fbpnp {
 // Zero padding on both ends of every line of the two line images of a stage.
 constexpr int kPad = 2;
 
-// One ray of one stage: Joseph samples on the major axis lines lo .. lo+n-1.
-// At line lo+k the minor-axis pixel-index coordinate is
-//   pos(k) = npos/2 + fma(k - n/2, dpos, pos_mid)      (integer npos/2, n/2)
-// with npos the number of pixels along the minor axis; ray weight
+// One ray of one stage: Joseph samples on the major-axis lines lo .. lo+n-1.
+// On line k the minor-axis pixel-index coordinate is
+//   pos(k) = npos/2 + fmaf(k - nlines/2, dpos, pos_c)     (integer npos/2, nlines/2)
+// with nlines, npos the grid sizes along the major and minor axis. The plan
+// chooses lo, n so that, with exactly this float evaluation, a line has a
+// sample if and only if pos(k) lies in [-1, npos). Ray weight
 // len = f h |d| / |d_major|.
 // bits: lo (16) | n (15) << 16 | axis << 31, axis 0 = x-major (lines are
 // columns, positions are rows), 1 = y-major (lines are rows, positions are
 // columns).
 struct alignas(16) RayRec {
-    float pos_mid, dpos, len;
+    float pos_c, dpos, len;
     uint32_t bits;
 };
 

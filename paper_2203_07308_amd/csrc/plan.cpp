@@ -43,11 +43,11 @@ fb_status validate_geometry(const fb_geom& g) {
     return FB_OK;
 }
 
-// Index range [lo, hi] of lines l in [0, nlines) with pos(l) = p0 + l*dp in (-1, npos).
-static void valid_range(double p0, double dp, int nlines, int npos, int& lo, int& hi) {
+// Index range [lo, hi] of lines l in [0, nlines) with pos(l) = p0 + l*dp in (pmin, pmax).
+static void valid_range(double p0, double dp, int nlines, double pmin, double pmax, int& lo, int& hi) {
     auto ok = [&](int l) {
         double p = p0 + (double)l * dp;
-        return p > -1.0 && p < (double)npos;
+        return p > pmin && p < pmax;
     };
     if (dp == 0.0) {
         if (ok(0)) {
@@ -59,7 +59,7 @@ static void valid_range(double p0, double dp, int nlines, int npos, int& lo, int
         }
         return;
     }
-    double a = (-1.0 - p0) / dp, b = ((double)npos - p0) / dp;
+    double a = (pmin - p0) / dp, b = (pmax - p0) / dp;
     if (a > b) std::swap(a, b);
     double flo = std::floor(a) + 1.0, fhi = std::ceil(b) - 1.0;
     flo = std::max(flo, 0.0);
@@ -122,20 +122,37 @@ fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays,
                 ylo = std::min(ylo, j);
                 yhi = std::max(yhi, j);
             }
+            // Float position of line k, centred on the grid's middle line and
+            // middle position (integers nlines/2, npos/2), exactly as the kernels
+            // evaluate it:  p(k) = fmaf(k - nlines/2, dpos, pos_c).
+            // A sample exists where p(k) lies in [-1, npos) - npos/2; p is monotone
+            // in k, so that is one interval of lines, found exactly in float from
+            // a slightly wider double-precision estimate.
+            const int lmid = nlines / 2, mid = npos / 2;
+            const float dpf = (float)dp;
+            const float pcf = (float)(p0 + (double)lmid * dp - (double)mid);
+            const float plo = (float)(-1 - mid), phi = (float)(npos - mid);
+            auto ok32 = [&](int l) {
+                const float q = std::fmaf((float)(l - lmid), dpf, pcf);
+                return q >= plo && q < phi;
+            };
+            // float and double positions differ by less than this margin, so the
+            // float interval lies inside the widened double one
+            const double margin = 1e-6 * (double)(nlines + npos + 100);
             int lo, hi;
-            valid_range(p0, dp, nlines, npos, lo, hi);
+            valid_range(p0, dp, nlines, -1.0 - margin, (double)npos + margin, lo, hi);
+            while (hi >= lo && !ok32(lo)) ++lo;
+            while (hi >= lo && !ok32(hi)) --hi;
             RayRec& r = rays[(size_t)k * nb + j];
             if (hi >= lo) {
                 const int n = hi - lo + 1;
-                // reference sample k = n/2, position relative to the integer npos/2:
-                // both keep the float magnitudes (and rounding) small
-                r.pos_mid = (float)(p0 + (double)(lo + n / 2) * dp - (double)(npos / 2));
-                r.dpos = (float)dp;
+                r.pos_c = pcf;
+                r.dpos = dpf;
                 r.len = (float)w;
                 r.bits = (uint32_t)lo | ((uint32_t)n << 16) | (xmajor ? 0u : 0x80000000u);
                 samples += n;
             } else {
-                r.pos_mid = 0.f;
+                r.pos_c = 0.f;
                 r.dpos = 0.f;
                 r.len = (float)w;
                 r.bits = xmajor ? 0u : 0x80000000u;

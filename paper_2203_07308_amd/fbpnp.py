@@ -55,6 +55,7 @@ class PnpArgs(ctypes.Structure):
         ("lambda_", ctypes.c_float), ("tau", ctypes.c_float), ("tv_iters", ctypes.c_int32),
         ("b", ctypes.c_void_p), ("y_prev", ctypes.c_void_p), ("x_prev", ctypes.c_void_p),
         ("x_out", ctypes.c_void_p), ("y_out", ctypes.c_void_p), ("history", ctypes.c_void_p),
+        ("next_stage", ctypes.c_int32), ("prepared", ctypes.c_int32),
     ]
 
 
@@ -239,7 +240,7 @@ def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float
                    _ptr(b, numel=plan.geom.n_views * plan.geom.n_bins, name="b"),
                    _ptr(y_prev, numel=npix, name="y_prev"), _ptr(x_prev, numel=npix, name="x_prev"),
                    _ptr(x_out, numel=npix, name="x_out"), _ptr(y_out, numel=npix, name="y_out"),
-                   _ptr(history, numel=npix, name="history"))
+                   _ptr(history, numel=npix, name="history"), -1, 0)
 
 
 def pnp_step(plan: Plan, args: PnpArgs, stream=None) -> None:

@@ -68,6 +68,7 @@ GEOMS = {
     "64": dict(n=64, V=90),
     "256": dict(n=256, V=360),
     "512": dict(n=512, V=720),
+    "1024": dict(n=1024, V=16),
     "ragged": dict(n=70, V=37, nb=101, ny=52, det_offset_mm=1.3, angle0_rad=0.2),
     "diag": dict(n=40, V=8, angle0_rad=math.pi / 4),
     "tiny": dict(n=8, V=4, nb=12),
@@ -76,7 +77,8 @@ GEOMS = {
 FP_CASES = [
     ("64", 1, None), ("64", 2, None), ("64", 4, None),
     ("256", 1, None), ("256", 2, None), ("256", 2, ("sub", 5, 8)),
-    ("512", 1, None), ("512", 2, None), ("512", 4, None), ("512", 1, ("sub", 3, 8)),
+    ("512", 1, None), ("512", 2, None), ("512", 4, None), ("512", 1, ("sub", 3, 8)), ("512", 1, ("sub", 1, 2)),
+    ("1024", 1, None),
     ("ragged", 1, None), ("ragged", 2, ("list", [36, 0, 17, 17, 5])),
     ("diag", 1, None), ("diag", 2, None), ("tiny", 1, None), ("tiny", 2, ("list", [2])),
 ]
@@ -174,6 +176,7 @@ def test_sketch_down_up_match_oracle(shape, f):
 
 @pytest.mark.parametrize("shape,lam,iters", [((64, 64), 0.01, 5), ((256, 256), 0.01, 5), ((512, 512), 0.01, 5),
                                              ((37, 70), 0.05, 3), ((96, 64), 0.02, 8), ((64, 80), 0.02, 21),
+                                             ((512, 512), 0.02, 8), ((520, 600), 0.01, 12),
                                              ((16, 16), 0.0, 5)])
 def test_tv_prox_matches_oracle(shape, lam, iters):
     say("tv", shape, lam, iters)
