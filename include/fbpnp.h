@@ -180,6 +180,37 @@ fb_status fb_graph_launch(fb_graph* graph, hipStream_t stream);
 fb_status fb_graph_destroy(fb_graph* graph);
 
 /*
+ * Reverse mode (differentiation of unrolled iterations).
+ *
+ * tv_prox_vjp: zbar = J^T xbar for the relaxed denoiser
+ *   z -> (1 - alpha) z + alpha tv_prox(z; lambda, n_iter, tau),
+ * recomputing the dual iterates; d|q|/dq is taken as 0 at q = 0. zbar must not
+ * alias z or xbar. ws: at least fb_tv_vjp_workspace_bytes(nx, ny, n_iter).
+ */
+size_t fb_tv_vjp_workspace_bytes(int nx, int ny, int n_iter);
+fb_status tv_prox_vjp(const float* z, const float* xbar, float* zbar, int nx, int ny, float lambda, int n_iter,
+                      float tau, float alpha, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * pnp_step_vjp: reverse mode of one pnp_step (Sec. 2.1, Algorithm 1) at the
+ * inputs in args (b, y_prev, views, sigma, eta, alpha, a_t, lambda, tau,
+ * tv_iters; x_out, y_out and history are ignored). Given the adjoints
+ * xbar = dL/dx_t and ybar = dL/dy_t (ybar may be NULL for 0), computes
+ *   xbar_prev = dL/dx_{t-1} = -a_t ybar            (may be NULL)
+ *   ybar_prev = dL/dy_{t-1} = zbar - eta H zbar,    zbar = J_relax^T (xbar + (1 + a_t) ybar)
+ *   eta_bar[0] = dL/deta_t = -<zbar, U G(y_prev)>   (device float)
+ * where H = sigma U (M A_s)^T M A_s S is the symmetric linear part of the
+ * sketched gradient G (the matched projector pair serves as its own adjoint).
+ * combine != 0 writes ybar_prev + xbar_prev into ybar_prev (the adjoint of
+ * x_0 when x_0 = y_0). Outputs must not alias inputs or each other. Uses the
+ * plan workspace and ws (at least fb_pnp_vjp_workspace_bytes(plan, tv_iters)).
+ */
+size_t fb_pnp_vjp_workspace_bytes(const fb_plan* plan, int tv_iters);
+fb_status pnp_step_vjp(const fb_plan* plan, const fb_pnp_args* args, const float* xbar, const float* ybar,
+                       float* xbar_prev, float* ybar_prev, float* eta_bar, int combine, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+
+/*
  * Lipschitz constant L = ||A_s D_f||_2^2 of the stage's data term over all
  * views (step eta = 1/L, Sec. 3) by n_iter power iterations from the constant
  * unit vector. Synchronous: blocks until the result is on the host.

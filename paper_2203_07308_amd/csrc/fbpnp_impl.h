@@ -73,4 +73,42 @@ fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays,
                              int64_t& samples);
 fb_status validate_geometry(const fb_geom& g);
 
+// ---- launch helpers (kernels.hip), used by the forward and reverse entry points
+constexpr int kRedBlocks = 256;  // blocks of the two-pass reductions
+constexpr int kTvMaxFused = 8;   // TV steps one launch can hold
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+fb_status check_launch(const char* what);
+fb_status check_stage(const fb_plan* p, int stage);
+fb_status check_views(const fb_plan* p, const int32_t* views, int n_sel);
+
+struct StageLines {
+    float* lx;   // x-major line image [nxs][pitch_x]
+    float* ly;   // y-major line image [nys][pitch_y], directly after lx
+    int ly_off;  // ly - lx in floats
+    int bytes;   // size of both images in bytes
+};
+StageLines stage_lines(const fb_plan* p, int stage);
+
+// Pooling D_f of x (ny x nx) into the stage's line images.
+fb_status launch_prepare(const fb_plan* p, int stage, const float* x, int nx, int f, hipStream_t s);
+// Projection of the selected views from the stage's line images (minus b when resid).
+fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* views, int n_sel, const float* b,
+                    float* y, hipStream_t s);
+// Backprojection: xo = scale A_s^T y (coarse), or fused: z = yprev - scale D^T-replicate(A_s^T y).
+fb_status launch_bp(const fb_plan* p, int stage, const float* y, const int32_t* views, int n_sel, float scale,
+                    float* xo, const float* yprev, float* z, bool fused, hipStream_t s);
+
+// Pooling target for the TV epilogue: the line images of the next stage.
+struct PoolTarget {
+    int f = 0;  // 0: none
+    float inv = 0.f;
+    float* lx = nullptr;
+    float* ly = nullptr;
+    int px = 0, py = 0, nxs = 0, nys = 0;
+};
+fb_status launch_tv_single(const float* z, int nx, int ny, float lam, float tau, int n_iter, const float* p_in,
+                           float* p_out, int mode, float alpha, float a_t, const float* x_prev, float* x_out,
+                           float* y_out, float* hist, hipStream_t s, const PoolTarget& pt = PoolTarget());
+
 }  // namespace fbpnp

@@ -534,7 +534,6 @@ __global__ __launch_bounds__(256) void k_fill(float* __restrict__ a, size_t n, f
 }
 
 // Per-block sums of squares in double, in a fixed order.
-constexpr int kRedBlocks = 256;
 __global__ __launch_bounds__(256) void k_sumsq_partial(const float* __restrict__ a, size_t n,
                                                        double* __restrict__ part) {
     __shared__ double s[256];
@@ -571,10 +570,12 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ w, 
         v[i] = w[i] * inv;
 }
 
+}  // namespace
+
 // ---------------------------------------------------------------------------
-// Host helpers
+// Host helpers (shared with the reverse-mode entry points)
 // ---------------------------------------------------------------------------
-inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+namespace fbpnp {
 
 fb_status check_launch(const char* what) {
     hipError_t e = hipGetLastError();
@@ -594,13 +595,6 @@ fb_status check_views(const fb_plan* p, const int32_t* views, int n_sel) {
     if (n_sel > p->g.n_views) return fail(FB_ESUBSET, "more selected views than views in the geometry");
     return FB_OK;
 }
-
-struct StageLines {
-    float* lx;    // x-major line image [nxs][pitch_x]
-    float* ly;    // y-major line image [nys][pitch_y], directly after lx
-    int ly_off;   // ly - lx in floats
-    int bytes;    // size of both images in bytes
-};
 
 // Line images of a stage live in one plan allocation, one region per stage.
 StageLines stage_lines(const fb_plan* p, int stage) {
@@ -651,8 +645,8 @@ fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* view
 }
 
 template <bool kFused>
-fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const int32_t* views, int n_sel, float scale,
-                      float* xo, const float* yprev, float* z, hipStream_t s) {
+static fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const int32_t* views, int n_sel,
+                             float scale, float* xo, const float* yprev, float* z, hipStream_t s) {
     const Stage& st = p->stages[stage];
     // pixels per lane: 4 x 4 on very large grids, 2 x 2 on large ones, 1
     // otherwise (more wavefronts); views split over up to 16 wavefronts per
@@ -692,20 +686,15 @@ fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const int32_t
     return check_launch("fanbeam_bp");
 }
 
-constexpr int kTvMaxFused = 8;
-
-// Pooling target for the TV epilogue: the line images of the next stage.
-struct PoolTarget {
-    int f = 0;  // 0: none
-    float inv = 0.f;
-    float* lx = nullptr;
-    float* ly = nullptr;
-    int px = 0, py = 0, nxs = 0, nys = 0;
-};
+fb_status launch_bp(const fb_plan* p, int stage, const float* y, const int32_t* views, int n_sel, float scale,
+                    float* xo, const float* yprev, float* z, bool fused, hipStream_t s) {
+    return fused ? launch_bp_t<true>(p, stage, y, views, n_sel, scale, xo, yprev, z, s)
+                 : launch_bp_t<false>(p, stage, y, views, n_sel, scale, xo, yprev, z, s);
+}
 
 fb_status launch_tv_single(const float* z, int nx, int ny, float lam, float tau, int n_iter, const float* p_in,
                            float* p_out, int mode, float alpha, float a_t, const float* x_prev, float* x_out,
-                           float* y_out, float* hist, hipStream_t s, const PoolTarget& pt = PoolTarget()) {
+                           float* y_out, float* hist, hipStream_t s, const PoolTarget& pt) {
     // 32 x 32 tiles with 1024 threads; 16 x 16 tiles when that leaves CUs idle
     const bool small = cdiv(nx, 32) * cdiv(ny, 32) < 256;
     const int T = small ? 16 : 32;
@@ -725,7 +714,7 @@ fb_status launch_tv_single(const float* z, int nx, int ny, float lam, float tau,
     return check_launch("tv_prox");
 }
 
-}  // namespace
+}  // namespace fbpnp
 
 // ===========================================================================
 // C ABI

@@ -1,0 +1,296 @@
+// Reverse mode of one PnP-MS2G iteration (Sec. 2.1, Algorithm 1) for
+// differentiating unrolled reconstructions: vector-Jacobian products of the
+// relaxed TV-prox denoiser and of a whole pnp_step, built from the matched
+// projector pair (the backprojector is the transpose of the projector, so the
+// symmetric Hessian part of the sketched gradient reuses both as they are).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "fbpnp_impl.h"
+
+using namespace fbpnp;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// TV-prox forward recomputation in global memory (one launch per half step).
+// The dual field p is zero outside the image and on the last row (p1) and
+// last column (p2), so div p needs no boundary tests; the gradient masks carry
+// the Neumann boundary.
+// ---------------------------------------------------------------------------
+
+// u = div p - z / lambda
+__global__ __launch_bounds__(256) void k_tvf_u(const float* __restrict__ p1, const float* __restrict__ p2,
+                                               const float* __restrict__ z, float il, int nx, int ny,
+                                               float* __restrict__ u) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= nx) return;
+    const size_t i = (size_t)r * nx + c;
+    const float up = r > 0 ? p1[i - nx] : 0.f, left = c > 0 ? p2[i - 1] : 0.f;
+    u[i] = (p1[i] - up) + (p2[i] - left) - z[i] * il;
+}
+
+// p' = (p + tau q) / (1 + tau |q|), q = masked forward differences of u
+__global__ __launch_bounds__(256) void k_tvf_p(const float* __restrict__ u, const float* __restrict__ p1,
+                                               const float* __restrict__ p2, float tau, int nx, int ny,
+                                               float* __restrict__ o1, float* __restrict__ o2) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= nx) return;
+    const size_t i = (size_t)r * nx + c;
+    const float q1 = r < ny - 1 ? u[i + nx] - u[i] : 0.f;
+    const float q2 = c < nx - 1 ? u[i + 1] - u[i] : 0.f;
+    const float inv = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(fmaf(q1, q1, q2 * q2)), 1.f));
+    o1[i] = fmaf(tau, q1, p1[i]) * inv;
+    o2[i] = fmaf(tau, q2, p2[i]) * inv;
+}
+
+// ---------------------------------------------------------------------------
+// TV-prox reverse sweep. With x = (1-alpha) z + alpha (z - lambda div p^K):
+//   zbar = xbar (direct), pbar^K = -lambda alpha div^T xbar,
+// and for n = K-1 .. 0, with N = p^n + tau q^n, d = 1 + tau |q^n|, p^{n+1} = N/d:
+//   Nbar = pbar/d, dbar = -<pbar, p^{n+1}>/d, qbar = tau Nbar + tau dbar q/|q|
+//   (0 at q = 0), pbar^n = Nbar + div^T ubar, zbar -= ubar/lambda,
+//   ubar = (masked grad)^T qbar.
+// (div^T w)_1[r,c] = [r < ny-1](w[r,c] - w[r+1,c]), likewise for columns.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tvb_init(const float* __restrict__ xbar, float lam_alpha, int nx, int ny,
+                                                  float* __restrict__ pb1, float* __restrict__ pb2,
+                                                  float* __restrict__ zbar) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= nx) return;
+    const size_t i = (size_t)r * nx + c;
+    const float xb = xbar[i];
+    zbar[i] = xb;
+    pb1[i] = r < ny - 1 ? -lam_alpha * (xb - xbar[i + nx]) : 0.f;
+    pb2[i] = c < nx - 1 ? -lam_alpha * (xb - xbar[i + 1]) : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_tvb_q(const float* __restrict__ u, const float* __restrict__ pn1,
+                                               const float* __restrict__ pn2, float tau, int nx, int ny,
+                                               float* __restrict__ pb1, float* __restrict__ pb2,
+                                               float* __restrict__ qb1, float* __restrict__ qb2) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= nx) return;
+    const size_t i = (size_t)r * nx + c;
+    const float q1 = r < ny - 1 ? u[i + nx] - u[i] : 0.f;
+    const float q2 = c < nx - 1 ? u[i + 1] - u[i] : 0.f;
+    const float mag = sqrtf(fmaf(q1, q1, q2 * q2));
+    const float den = fmaf(tau, mag, 1.f);
+    const float b1 = pb1[i], b2 = pb2[i];
+    const float nb1 = b1 / den, nb2 = b2 / den;
+    const float db = -fmaf(b1, pn1[i], b2 * pn2[i]) / den;
+    const float mb = mag > 0.f ? tau * db / mag : 0.f;
+    qb1[i] = fmaf(tau, nb1, mb * q1);
+    qb2[i] = fmaf(tau, nb2, mb * q2);
+    pb1[i] = nb1;
+    pb2[i] = nb2;
+}
+
+// ubar at (rr, cc): transpose of the masked forward differences applied to qbar
+__device__ __forceinline__ float ubar_at(const float* __restrict__ qb1, const float* __restrict__ qb2, int rr, int cc,
+                                         int nx, int ny) {
+    const size_t i = (size_t)rr * nx + cc;
+    float s = 0.f;
+    if (rr < ny - 1) s -= qb1[i];
+    if (rr > 0) s += qb1[i - nx];
+    if (cc < nx - 1) s -= qb2[i];
+    if (cc > 0) s += qb2[i - 1];
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_tvb_up(const float* __restrict__ qb1, const float* __restrict__ qb2,
+                                                float il, int nx, int ny, float* __restrict__ pb1,
+                                                float* __restrict__ pb2, float* __restrict__ zbar) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= nx) return;
+    const size_t i = (size_t)r * nx + c;
+    const float u0 = ubar_at(qb1, qb2, r, c, nx, ny);
+    if (r < ny - 1) pb1[i] += u0 - ubar_at(qb1, qb2, r + 1, c, nx, ny);
+    if (c < nx - 1) pb2[i] += u0 - ubar_at(qb1, qb2, r, c + 1, nx, ny);
+    zbar[i] -= u0 * il;
+}
+
+// ---------------------------------------------------------------------------
+// pnp_step reverse helpers
+// ---------------------------------------------------------------------------
+
+// z = y_prev - (eta / f^2) gs[r/f][c/f];  xtot = xbar + (1 + a) ybar;  xbar_prev = -a ybar
+__global__ __launch_bounds__(256) void k_vjp_front(const float* __restrict__ yprev, const float* __restrict__ gs,
+                                                   int f, int nxs, float step, const float* __restrict__ xbar,
+                                                   const float* __restrict__ ybar, float a_t, int nx,
+                                                   float* __restrict__ z, float* __restrict__ xtot,
+                                                   float* __restrict__ xbar_prev) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= nx) return;
+    const size_t i = (size_t)r * nx + c;
+    z[i] = yprev[i] - step * gs[(size_t)(r / f) * nxs + c / f];
+    const float yb = ybar ? ybar[i] : 0.f;
+    xtot[i] = fmaf(1.f + a_t, yb, xbar[i]);
+    if (xbar_prev) xbar_prev[i] = -a_t * yb;
+}
+
+// per-block partial sums of zbar[r][c] * gs[r/f][c/f] in double, fixed order
+__global__ __launch_bounds__(256) void k_dot_rep(const float* __restrict__ zb, const float* __restrict__ gs, int f,
+                                                 int nxs, int nx, size_t n, double* __restrict__ part) {
+    __shared__ double sm[256];
+    double acc = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i / nx), c = (int)(i - (size_t)r * nx);
+        acc += (double)zb[i] * (double)gs[(size_t)(r / f) * nxs + c / f];
+    }
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ part, int nparts, double scale,
+                                                   float* __restrict__ out) {
+    __shared__ double sm[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += part[i];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (float)(scale * sm[0]);
+}
+
+__global__ __launch_bounds__(256) void k_zero(float* __restrict__ y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) y[i] = 0.f;
+}
+
+// y += a x
+__global__ __launch_bounds__(256) void k_axpy(const float* __restrict__ x, float a, size_t n, float* __restrict__ y) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = fmaf(a, x[i], y[i]);
+}
+
+size_t tv_ws_floats(int nx, int ny, int n_iter) {
+    // p levels 0..K (two planes each), u levels 0..K-1, pbar, qbar
+    return (size_t)nx * ny * (size_t)(2 * (n_iter + 1) + n_iter + 4);
+}
+
+// zbar = J^T xbar for z -> (1 - alpha) z + alpha TV_prox(z); ws holds tv_ws_floats.
+fb_status launch_tv_vjp(const float* z, const float* xbar, float* zbar, int nx, int ny, float lam, int K, float tau,
+                        float alpha, float* ws, hipStream_t s) {
+    const size_t n = (size_t)nx * ny;
+    dim3 grid(cdiv(nx, 256), ny);
+    if (lam == 0.f || K == 0 || alpha == 0.f) {
+        hipError_t e = hipMemcpyAsync(zbar, xbar, n * sizeof(float), hipMemcpyDeviceToDevice, s);
+        return e == hipSuccess ? FB_OK : hip_fail(e, "tv vjp copy");
+    }
+    float* P = ws;                       // level k: P + 2 k n (p1), + n (p2)
+    float* U = P + 2 * (size_t)(K + 1) * n;  // level k: U + k n
+    float* pb1 = U + (size_t)K * n;
+    float* pb2 = pb1 + n;
+    float* qb1 = pb2 + n;
+    float* qb2 = qb1 + n;
+    const float il = 1.f / lam;
+    k_zero<<<cdiv((int)std::min<size_t>(2 * n, 1 << 20), 256), 256, 0, s>>>(P, 2 * n);  // p^0 = 0
+    for (int k = 0; k < K; ++k) {
+        float* p1 = P + 2 * (size_t)k * n;
+        k_tvf_u<<<grid, 256, 0, s>>>(p1, p1 + n, z, il, nx, ny, U + (size_t)k * n);
+        k_tvf_p<<<grid, 256, 0, s>>>(U + (size_t)k * n, p1, p1 + n, tau, nx, ny, p1 + 2 * n, p1 + 3 * n);
+    }
+    k_tvb_init<<<grid, 256, 0, s>>>(xbar, lam * alpha, nx, ny, pb1, pb2, zbar);
+    for (int k = K - 1; k >= 0; --k) {
+        float* pn = P + 2 * (size_t)(k + 1) * n;
+        k_tvb_q<<<grid, 256, 0, s>>>(U + (size_t)k * n, pn, pn + n, tau, nx, ny, pb1, pb2, qb1, qb2);
+        k_tvb_up<<<grid, 256, 0, s>>>(qb1, qb2, il, nx, ny, pb1, pb2, zbar);
+    }
+    return check_launch("tv_prox_vjp");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fb_tv_vjp_workspace_bytes(int nx, int ny, int n_iter) {
+    if (nx < 1 || ny < 1 || n_iter < 0) return 0;
+    return tv_ws_floats(nx, ny, n_iter) * sizeof(float);
+}
+
+fb_status tv_prox_vjp(const float* z, const float* xbar, float* zbar, int nx, int ny, float lambda, int n_iter,
+                      float tau, float alpha, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!z || !xbar || !zbar || nx < 1 || ny < 1 || n_iter < 0) return fail(FB_EINVAL, "tv_prox_vjp: bad arguments");
+    if (!(lambda >= 0.f) || !(tau > 0.f)) return fail(FB_EINVAL, "tv_prox_vjp: need lambda >= 0 and tau > 0");
+    if (zbar == xbar || zbar == z) return fail(FB_EINVAL, "tv_prox_vjp: zbar must not alias the inputs");
+    if (!ws || ws_bytes < fb_tv_vjp_workspace_bytes(nx, ny, n_iter))
+        return fail(FB_EINVAL, "tv_prox_vjp: workspace too small");
+    return launch_tv_vjp(z, xbar, zbar, nx, ny, lambda, n_iter, tau, alpha, (float*)ws, stream);
+}
+
+size_t fb_pnp_vjp_workspace_bytes(const fb_plan* p, int tv_iters) {
+    if (!p || tv_iters < 0) return 0;
+    const size_t n = (size_t)p->g.nx * p->g.ny;
+    // z, xtot, zbar, coarse gradient, TV reverse sweep, reduction partials (+1 result)
+    return (4 * n + tv_ws_floats(p->g.nx, p->g.ny, tv_iters)) * sizeof(float) + (kRedBlocks + 2) * sizeof(double);
+}
+
+fb_status pnp_step_vjp(const fb_plan* p, const fb_pnp_args* a, const float* xbar, const float* ybar, float* xbar_prev,
+                       float* ybar_prev, float* eta_bar, int combine, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!a || !xbar || !ybar_prev || !eta_bar) return fail(FB_EINVAL, "pnp_step_vjp: null argument");
+    fb_status st = check_stage(p, a->stage);
+    if (st != FB_OK) return st;
+    if ((st = check_views(p, a->views, a->n_sel)) != FB_OK) return st;
+    if (!a->b || !a->y_prev) return fail(FB_EINVAL, "pnp_step_vjp: null buffer in args");
+    if (a->tv_iters < 0 || a->tv_iters > 64) return fail(FB_EINVAL, "pnp_step_vjp: tv_iters out of range");
+    if (!(a->lambda >= 0.f) || !(a->tau > 0.f)) return fail(FB_EINVAL, "pnp_step_vjp: need lambda >= 0 and tau > 0");
+    if (!ws || ws_bytes < fb_pnp_vjp_workspace_bytes(p, a->tv_iters))
+        return fail(FB_EINVAL, "pnp_step_vjp: workspace too small");
+    const float* outs[] = {xbar_prev, ybar_prev};
+    const float* ins[] = {xbar, ybar, a->y_prev, a->x_prev, a->b};
+    for (const float* o : outs)
+        for (const float* q : ins)
+            if (o && o == q) return fail(FB_EINVAL, "pnp_step_vjp: outputs must not alias inputs");
+    if (xbar_prev && xbar_prev == ybar_prev) return fail(FB_EINVAL, "pnp_step_vjp: xbar_prev aliases ybar_prev");
+    const Stage& S = p->stages[a->stage];
+    const int nx = p->g.nx, ny = p->g.ny, f = S.f;
+    const size_t n = (size_t)nx * ny;
+    float* z = (float*)ws;
+    float* xtot = z + n;
+    float* zbar = xtot + n;
+    float* gs = zbar + n;
+    float* tvws = gs + n;
+    double* part = (double*)((char*)ws + (4 * n + tv_ws_floats(nx, ny, a->tv_iters)) * sizeof(float));
+    const dim3 grid(cdiv(nx, 256), ny);
+    // forward recomputation: gs = sigma A_s^T M (M A_s S y - M b), z = y - eta U gs
+    if ((st = launch_prepare(p, a->stage, a->y_prev, nx, f, stream)) != FB_OK) return st;
+    if ((st = launch_fp(p, a->stage, true, a->views, a->n_sel, a->b, p->resid, stream)) != FB_OK) return st;
+    if ((st = launch_bp(p, a->stage, p->resid, a->views, a->n_sel, a->sigma, gs, nullptr, nullptr, false, stream)) !=
+        FB_OK)
+        return st;
+    const float inv_ff = 1.f / (float)(f * f);
+    k_vjp_front<<<grid, 256, 0, stream>>>(a->y_prev, gs, f, S.nxs, a->eta * inv_ff, xbar, ybar, a->a_t, nx, z, xtot,
+                                          combine ? nullptr : xbar_prev);
+    if ((st = check_launch("pnp_step_vjp front")) != FB_OK) return st;
+    // zbar = J_relax^T xtot
+    const int K = a->lambda > 0.f ? a->tv_iters : 0;
+    if ((st = launch_tv_vjp(z, xtot, zbar, nx, ny, a->lambda, K, a->tau, a->alpha, tvws, stream)) != FB_OK) return st;
+    // eta_bar = -<zbar, U gs>
+    k_dot_rep<<<kRedBlocks, 256, 0, stream>>>(zbar, gs, f, S.nxs, nx, n, part);
+    k_dot_final<<<1, 256, 0, stream>>>(part, kRedBlocks, -(double)inv_ff, eta_bar);
+    if ((st = check_launch("pnp_step_vjp eta")) != FB_OK) return st;
+    // ybar_prev = zbar - eta sigma U A_s^T M^T M A_s S zbar
+    if ((st = launch_prepare(p, a->stage, zbar, nx, f, stream)) != FB_OK) return st;
+    if ((st = launch_fp(p, a->stage, false, a->views, a->n_sel, nullptr, p->resid, stream)) != FB_OK) return st;
+    if ((st = launch_bp(p, a->stage, p->resid, a->views, a->n_sel, a->eta * a->sigma * inv_ff, nullptr, zbar, ybar_prev,
+                        true, stream)) != FB_OK)
+        return st;
+    if (combine && ybar) {
+        // adjoint of x_0 = y_0: ybar_prev + xbar_prev, xbar_prev = -a ybar
+        k_axpy<<<cdiv((int)std::min<size_t>(n, 1 << 20), 256), 256, 0, stream>>>(ybar, -a->a_t, n, ybar_prev);
+        if ((st = check_launch("pnp_step_vjp combine")) != FB_OK) return st;
+    }
+    return FB_OK;
+}
+
+}  // extern "C"

@@ -23,7 +23,8 @@ _STATUS = {-1: "FB_EINVAL", -2: "FB_EGEOM", -3: "FB_EDIV", -4: "FB_ESUBSET", -5:
 EXPORTS = [
     "fb_last_error", "fb_plan_create", "fb_plan_destroy", "fb_plan_stage_info", "fanbeam_fp", "fanbeam_bp",
     "sketch_down", "sketch_up", "fb_tv_workspace_bytes", "tv_prox", "pnp_step", "fb_graph_create",
-    "fb_graph_launch", "fb_graph_destroy", "fb_power_lipschitz",
+    "fb_graph_launch", "fb_graph_destroy", "fb_tv_vjp_workspace_bytes", "tv_prox_vjp",
+    "fb_pnp_vjp_workspace_bytes", "pnp_step_vjp", "fb_power_lipschitz",
 ]
 
 
@@ -89,8 +90,15 @@ def load() -> ctypes.CDLL:
     lib.fb_graph_launch.argtypes = [vp, vp]
     lib.fb_graph_destroy.argtypes = [vp]
     lib.fb_power_lipschitz.argtypes = [vp, c_int, c_int, P(ctypes.c_double), vp]
+    lib.fb_tv_vjp_workspace_bytes.argtypes = [c_int, c_int, c_int]
+    lib.fb_tv_vjp_workspace_bytes.restype = ctypes.c_size_t
+    lib.tv_prox_vjp.argtypes = [vp, vp, vp, c_int, c_int, c_float, c_int, c_float, c_float, vp, ctypes.c_size_t, vp]
+    lib.fb_pnp_vjp_workspace_bytes.argtypes = [vp, c_int]
+    lib.fb_pnp_vjp_workspace_bytes.restype = ctypes.c_size_t
+    lib.pnp_step_vjp.argtypes = [vp, P(PnpArgs), vp, vp, vp, vp, vp, c_int, vp, ctypes.c_size_t, vp]
     for name in EXPORTS:
-        if name not in ("fb_last_error", "fb_tv_workspace_bytes"):
+        if name not in ("fb_last_error", "fb_tv_workspace_bytes", "fb_tv_vjp_workspace_bytes",
+                        "fb_pnp_vjp_workspace_bytes"):
             getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -270,6 +278,35 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def tv_prox_vjp(z: torch.Tensor, xbar: torch.Tensor, zbar: torch.Tensor, lam: float, n_iter: int = 5,
+                tau: float = 0.125, alpha: float = 1.0, ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """zbar = J^T xbar of z -> (1 - alpha) z + alpha tv_prox(z)."""
+    ny, nx = z.shape
+    need = int(load().fb_tv_vjp_workspace_bytes(nx, ny, n_iter))
+    if ws is None:
+        ws = torch.empty((need + 3) // 4, dtype=torch.float32, device=z.device)
+    _check(load().tv_prox_vjp(_ptr(z, name="z"), _ptr(xbar, numel=nx * ny, name="xbar"),
+                              _ptr(zbar, numel=nx * ny, name="zbar"), nx, ny, float(lam), int(n_iter), float(tau),
+                              float(alpha), ctypes.c_void_p(ws.data_ptr()), ws.numel() * 4, _stream(stream)))
+    return zbar
+
+
+def pnp_vjp_workspace(plan: Plan, tv_iters: int = 5, device="cuda") -> torch.Tensor:
+    need = int(load().fb_pnp_vjp_workspace_bytes(plan.handle, tv_iters))
+    return torch.empty((need + 3) // 4, dtype=torch.float32, device=device)
+
+
+def pnp_step_vjp(plan: Plan, args: PnpArgs, xbar: torch.Tensor, ybar: torch.Tensor | None,
+                 xbar_prev: torch.Tensor | None, ybar_prev: torch.Tensor, eta_bar: torch.Tensor,
+                 ws: torch.Tensor, combine: bool = False, stream=None) -> None:
+    """Reverse mode of one pnp_step (see include/fbpnp.h)."""
+    npix = plan.geom.nx * plan.geom.ny
+    _check(load().pnp_step_vjp(plan.handle, ctypes.byref(args), _ptr(xbar, numel=npix, name="xbar"),
+                               _ptr(ybar, numel=npix, name="ybar"), _ptr(xbar_prev, numel=npix, name="xbar_prev"),
+                               _ptr(ybar_prev, numel=npix, name="ybar_prev"), _ptr(eta_bar, name="eta_bar"),
+                               int(combine), ctypes.c_void_p(ws.data_ptr()), ws.numel() * 4, _stream(stream)))
 
 
 def power_lipschitz(plan: Plan, stage: int, n_iter: int = 100, stream=None) -> float:
