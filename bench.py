@@ -32,9 +32,45 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 # algorithmic FP32 operations per unit of work
 FLOP_PER_FP_SAMPLE = 7      # position fma (2), fraction (1), interpolation sub+fma (3), accumulate (1)
+FLOP_PER_FP_RAY = 2         # length scaling and residual subtraction
 FLOP_PER_BP_SAMPLE = 8      # position fma (2), fraction (1), 1-w (1), two weighted fma (4)
+FLOP_PER_BP_FINE_PIXEL = 2  # z = y_prev - scale * (U g)
 FLOP_PER_TV_PIXEL_ITER = 20
 FLOP_PER_TV_PIXEL_OUT = 8
+KERNEL_DESCRIPTION = {"fp": "Joseph forward projection minus b", "bp": "matched gather back-projection fused with the "
+                      "gradient step", "tv": "TV-prox with relaxation, momentum and pooling epilogue"}
+KERNEL_SOURCES = ["paper_2203_07308_amd/csrc/kernels.hip", "paper_2203_07308_amd/csrc/fbpnp_impl.h",
+                  "paper_2203_07308_amd/csrc/plan.cpp"]
+TRAFFIC_SUMMARY = "profiles/ms2g512_hbm_traffic.md"
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the kernel sources: hardware-counter figures are valid only for this text."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def launch_traffic(key: str, path: str | None = None):
+    """HBM bytes per launch of kernel group `key` (e.g. "bp_f1") from the committed
+    counter summary, or None when it is missing or was taken from other kernel sources."""
+    import re
+
+    path = path or os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    text = open(path).read()
+    m = re.search(r"kernel sources sha256: `([0-9a-f]{64})`", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None, "counter summary predates the current kernel sources"
+    m = re.search(r"^\| " + re.escape(key) + r" \|(?:[^|\n]*\|){6}\s*([0-9]+)\s*\|", text, re.M)
+    if not m:
+        return None, f"no {key} row in the counter summary"
+    return int(m.group(1)), TRAFFIC_SUMMARY
 
 
 def log(*a):
@@ -52,6 +88,14 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="short run for hardware-counter passes: two replays of the sketched schedule "
                          "and a 64 MiB device copy (counter calibration); prints no JSON line")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="print a markdown summary of a rocprofv3 --kernel-trace --stats -f csv output directory "
+                         "(no GPU use)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the HBM traffic summary of two rocprofv3 --pmc runs of --profile "
+                         "(FETCH_SIZE, then WRITE_SIZE), calibrated by the 64 MiB copy (no GPU use)")
+    ap.add_argument("--cmd", default="", help="command line quoted in a summary")
+    ap.add_argument("--bench-log", help="log of the profiled command (its JSON line is quoted in a trace summary)")
     return ap.parse_args()
 
 
@@ -73,8 +117,136 @@ class Events:
         self.ms = self.a.elapsed_time(self.b)
 
 
+def _short(name: str) -> str:
+    name = name.replace("void ", "").replace("(anonymous namespace)::", "")
+    return name[: name.index("(")] if "(" in name else name
+
+
+def _csv(directory: str, suffix: str):
+    import csv
+    import glob
+
+    files = sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def label_dispatches(names):
+    """(group, index) labels of the dispatches that belong to complete replays of the
+    sketched schedule, e.g. ("bp_f1", i): a replay starts at the pooling kernel followed by
+    the first residual projection and has one denoiser launch per iteration."""
+    from paper_2203_07308_amd import synth
+
+    w = synth.WORKLOADS["ms2g512"]
+    stage_f = [f for f, n in w.stages for _ in range(n)]
+    T = len(stage_f)
+    cls = {"k_fp": "fp", "k_bp": "bp", "k_tv": "tv", "k_prepare": "prepare"}
+    out = []
+    i = 0
+    while i + 1 < len(names):
+        if not (names[i] == "k_prepare" and names[i + 1].startswith("k_fp<true")):
+            i += 1
+            continue
+        lab, t, j = [], 0, i
+        while j < len(names) and t < T:
+            c = next((v for k, v in cls.items() if names[j].startswith(k)), None)
+            if c is None:
+                break
+            lab.append((f"{c}_f{stage_f[t]}", j))
+            t += c == "tv"
+            j += 1
+        if t == T:
+            out += lab
+        i = j
+    return out
+
+
+def trace_summary(args) -> int:
+    stats = _csv(args.trace_summary, "kernel_stats.csv")
+    trace = _csv(args.trace_summary, "kernel_trace.csv")
+    trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+    names = [_short(r["Kernel_Name"]) for r in trace]
+    out = ["# rocprofv3 kernel trace: 512x512 multi-stage sketched PnP-SGD (720 views x 768 bins, f = 4, 2, 1, "
+           "1 of 8 view subsets)", "", "Command (repository root, one MI355X, library built):", "", "```",
+           args.cmd, "```", "", "Summary: `python bench.py --trace-summary <output dir> --cmd '<command>'"
+           + (" --bench-log <log>" if args.bench_log else "") + "`", "",
+           "## Kernel statistics over the whole run (rocprofv3 --stats)", "",
+           "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in stats[:20]:
+        out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    groups = {}
+    for g, j in label_dispatches(names):
+        groups.setdefault(g, []).append(j)
+    n_rep = len(groups.get("tv_f1", [])) // 20 if groups else 0
+    out += ["", f"## Per iteration group, over {n_rep} complete replays of the schedule (graph and direct calls)", "",
+            "| group | kernel | launches | avg us | min us | max us | us per replay |", "|---|---|---|---|---|---|---|"]
+    for g in sorted(groups, key=lambda k: (k.split("_f")[0], -int(k.split("_f")[1]))):
+        d = [(int(trace[j]["End_Timestamp"]) - int(trace[j]["Start_Timestamp"])) / 1e3 for j in groups[g]]
+        kn = sorted(set(names[j] for j in groups[g]))
+        out.append(f"| {g} | {', '.join('`' + k + '`' for k in kn)} | {len(d)} | {sum(d) / len(d):.2f} | "
+                   f"{min(d):.2f} | {max(d):.2f} | {sum(d) / max(n_rep, 1):.1f} |")
+    if args.bench_log:
+        lines = [ln for ln in open(args.bench_log) if ln.startswith("{")]
+        if lines:
+            res = json.loads(lines[-1])
+            out += ["", "## The profiled command's own result line (HIP-event kernel timing)", "",
+                    f"- value: {res['value']} {res['unit']} ({res['ms_per_step']} ms per step)",
+                    f"- roofline: `{json.dumps(res['roofline'])}`"]
+    print("\n".join(out))
+    return 0
+
+
+def pmc_summary(args) -> int:
+    fetch = _csv(args.pmc_summary[0], "counter_collection.csv")
+    write = _csv(args.pmc_summary[1], "counter_collection.csv")
+    out = ["# HBM traffic per launch: 512x512 multi-stage sketched PnP-SGD (rocprofv3 --pmc)", "",
+           "Commands (repository root, one MI355X, library built), one counter per pass:", "", "```", args.cmd, "```",
+           "", "Summary: `python bench.py --pmc-summary <FETCH_SIZE dir> <WRITE_SIZE dir> --cmd '<commands>'`", "",
+           f"kernel sources sha256: `{kernel_source_hash()}`", ""]
+    per = {}
+    for rows, cname in ((fetch, "FETCH_SIZE"), (write, "WRITE_SIZE")):
+        rows = [r for r in rows if r["Counter_Name"] == cname]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        names = [_short(r["Kernel_Name"]) for r in rows]
+        copies = [r for r, n in zip(rows, names) if n == "__amd_rocclr_copyBuffer"]
+        if not copies:
+            raise SystemExit("no copy kernel for the calibration")
+        copy_kib = float(copies[-1]["Counter_Value"])  # the 64 MiB device copy at the end of --profile
+        factor = 65536.0 / copy_kib
+        per[cname] = {"copy_kib": copy_kib, "factor": factor, "groups": {}}
+        for g, j in label_dispatches(names):
+            per[cname]["groups"].setdefault(g, []).append((names[j], float(rows[j]["Counter_Value"])))
+    cf, cw = per["FETCH_SIZE"]["factor"], per["WRITE_SIZE"]["factor"]
+    out += ["Calibration: a 64 MiB device-to-device copy (`__amd_rocclr_copyBuffer`) reads FETCH_SIZE = "
+            f"{per['FETCH_SIZE']['copy_kib']:.0f} KiB and WRITE_SIZE = {per['WRITE_SIZE']['copy_kib']:.0f} KiB, "
+            f"so bytes = FETCH_SIZE x 1024 x {cf:.4f} and WRITE_SIZE x 1024 x {cw:.4f}.", "",
+            "| group | kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read bytes | written bytes | "
+            "traffic bytes per launch |", "|---|---|---|---|---|---|---|---|"]
+    groups = per["FETCH_SIZE"]["groups"]
+    for g in sorted(groups, key=lambda k: (k.split("_f")[0], -int(k.split("_f")[1]))):
+        fv = [v for _, v in groups[g]]
+        wv = [v for _, v in per["WRITE_SIZE"]["groups"].get(g, [])]
+        if not wv:
+            continue
+        fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)
+        rb, wb = fk * 1024 * cf, wk * 1024 * cw
+        kn = sorted(set(n for n, _ in groups[g]))
+        out.append(f"| {g} | {', '.join('`' + k + '`' for k in kn)} | {len(fv)} | {fk:.1f} | {wk:.1f} | "
+                   f"{rb:.0f} | {wb:.0f} | {rb + wb:.0f} |")
+    print("\n".join(out))
+    return 0
+
+
 def main() -> int:
     args = parse()
+    if args.trace_summary:
+        return trace_summary(args)
+    if args.pmc_summary:
+        return pmc_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -126,13 +298,14 @@ def main() -> int:
                 t += 1
         return out
 
-    def make_steps(sched, hist=None):
+    def make_steps(sched, hist=None, events=None):
         steps = []
         for t, (f, s, a_t) in enumerate(sched):
             views = None if s is None else subsets[s]
             sigma = 1.0 if s is None else float(n_sub)
             steps.append(fbpnp.pnp_args(plan, stage_of[f], b, y, x, x, y, eta[f], a_t, views, sigma, w.alpha, w.lam,
-                                        w.tau, w.tv_iters, None if hist is None else hist[t]))
+                                        w.tau, w.tv_iters, None if hist is None else hist[t],
+                                        None if events is None else events[t]))
         return steps
 
     sk_sched = schedule(w.stages, 3000 * w.seed_base, n_sub)
@@ -143,6 +316,13 @@ def main() -> int:
         x.zero_()
         y.zero_()
         g.launch()
+
+    def run_once_direct(steps):
+        x.zero_()
+        y.zero_()
+        for st in steps:
+            fbpnp.pnp_step(plan, st)
+        torch.cuda.synchronize()
 
     if args.profile:
         for _ in range(2):
@@ -166,63 +346,47 @@ def main() -> int:
     iters_per_s = T * args.steps / (ev.ms * 1e-3)
     log(f"sketched schedule: {ms_per_step:.3f} ms per {T}-iteration reconstruction, {iters_per_s:.0f} it/s")
 
-    # ---- per-kernel timings (standalone entry points, same stream, back-to-back launches)
-    kernels = {}
+    # ---- per-kernel durations: the same schedule by direct pnp_step calls (with the graph's
+    # pooling hand-over), each projector / denoiser kernel started with HIP start/stop events
+    # on the launch stream (hipExtLaunchKernelGGL), so an event pair spans exactly one kernel
     reps = args.kernel_reps
-    sub0 = subsets[0]
-    n_sel = sub0.numel()
-    samples = {f: plan.stage_info(stage_of[f]).samples_all_views for f in factors}
-    sino = torch.empty(V * B, device="cuda")
-    for f in factors:
-        s = stage_of[f]
-        ns = (N // f) ** 2
-        v = torch.rand(ns, device="cuda")
-        r = torch.rand(n_sel * B, device="cuda")
-        out = torch.empty(ns, device="cuda")
-        for name, call in (("fp", lambda: fbpnp.fanbeam_fp(plan, s, v, sino[: n_sel * B], sub0)),
-                           ("bp", lambda: fbpnp.fanbeam_bp(plan, s, r, out, sub0))):
-            call()
-            torch.cuda.synchronize()
-            with Events(torch) as ev:
-                for _ in range(reps):
-                    call()
-            per = ev.ms / reps
-            smp = samples[f] * n_sel / V  # one subset of interleaved views: V/n_sub of the views
-            flop = smp * (FLOP_PER_FP_SAMPLE if name == "fp" else FLOP_PER_BP_SAMPLE)
-            kernels[f"{name}_f{f}_subset"] = dict(ms=per, samples=smp, gups=smp / (per * 1e-3) / 1e9,
-                                                   tflops=flop / (per * 1e-3) / 1e12, launches_per_step=20)
-    zz = torch.rand(npix, device="cuda")
-    xo = torch.empty(npix, device="cuda")
-    fbpnp.tv_prox(zz.reshape(N, N), xo.reshape(N, N), w.lam, w.tv_iters, w.tau)
-    torch.cuda.synchronize()
-    with Events(torch) as ev:
-        for _ in range(reps):
-            fbpnp.tv_prox(zz.reshape(N, N), xo.reshape(N, N), w.lam, w.tv_iters, w.tau)
-    per = ev.ms / reps
-    tv_flop = npix * (w.tv_iters * FLOP_PER_TV_PIXEL_ITER + FLOP_PER_TV_PIXEL_OUT)
-    kernels["tv_512"] = dict(ms=per, tflops=tv_flop / (per * 1e-3) / 1e12, launches_per_step=T)
-    # full-resolution, all-view projector GUPS (the full-gradient comparator's operator)
-    vfull = torch.rand(npix, device="cuda")
-    rfull = torch.rand(V * B, device="cuda")
-    for name, call in (("fp", lambda: fbpnp.fanbeam_fp(plan, s_full, vfull, sino)),
-                       ("bp", lambda: fbpnp.fanbeam_bp(plan, s_full, rfull, xo))):
-        call()
-        torch.cuda.synchronize()
-        with Events(torch) as ev:
-            for _ in range(reps):
-                call()
-        per = ev.ms / reps
-        smp = samples[1]
-        kernels[f"{name}_f1_allviews"] = dict(ms=per, samples=smp, gups=smp / (per * 1e-3) / 1e9,
-                                              conventional_gups=V * npix / (per * 1e-3) / 1e9,
-                                              launches_per_step=0)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(T)]
+    tsteps = make_steps(sk_sched, events=evs)
+    fbpnp.chain_steps(tsteps)
+    vsamp = {f: plan.view_samples(stage_of[f]) for f in factors}
+    sub_views = [synth.subset_views(s, n_sub, V) for s in range(n_sub)]
+    acc = {}
+    for _ in range(reps):
+        run_once_direct(tsteps)
+        for t, (f, s, _a) in enumerate(sk_sched):
+            smp = sum(vsamp[f][v] for v in sub_views[s])
+            n_fine = npix
+            flops = {"fp": FLOP_PER_FP_SAMPLE * smp + FLOP_PER_FP_RAY * len(sub_views[s]) * B,
+                     "bp": FLOP_PER_BP_SAMPLE * smp + FLOP_PER_BP_FINE_PIXEL * n_fine,
+                     "tv": n_fine * (w.tv_iters * FLOP_PER_TV_PIXEL_ITER + FLOP_PER_TV_PIXEL_OUT)}
+            for k, name in ((0, "fp"), (2, "bp"), (4, "tv")):
+                a_ = acc.setdefault((name, f), {"ms": 0.0, "n": 0, "flop": 0.0, "samples": 0})
+                a_["ms"] += evs[t][k].elapsed_time(evs[t][k + 1])
+                a_["n"] += 1
+                a_["flop"] += flops[name]
+                a_["samples"] += smp if name != "tv" else 0
+    kernels = {}
+    for (name, f), a_ in acc.items():
+        sec = a_["ms"] * 1e-3
+        kernels[f"{name}_f{f}"] = dict(
+            avg_launch_us=1e3 * a_["ms"] / a_["n"], launches_per_step=a_["n"] // reps,
+            us_per_step=1e3 * a_["ms"] / reps, flop_per_launch=a_["flop"] / a_["n"],
+            tflops=a_["flop"] / sec / 1e12,
+            **({"gsamples_per_s": a_["samples"] / sec / 1e9} if name != "tv" else {}))
     for k, v in kernels.items():
         log(f"  {k}: {v}")
-    dom_name, dom = max(((k, v) for k, v in kernels.items() if v["launches_per_step"] > 0),
-                        key=lambda kv: kv[1]["ms"] * kv[1]["launches_per_step"])
-    roofline = {"kernel": dom_name, "bound": "alu", "achieved": round(dom["tflops"], 4),
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(dom["tflops"] / PEAK_FP32_TFLOPS, 5),
-                "traffic": None, "avg_launch_ms": round(dom["ms"], 5)}
+    dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["us_per_step"])
+    traffic, traffic_src = launch_traffic(dom_name)
+    roofline = {"kernel": f"{dom_name} ({KERNEL_DESCRIPTION[dom_name[:2]]}, pooling factor {dom_name[4:]})",
+                "bound": "alu", "achieved": round(dom["tflops"], 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(dom["tflops"] / PEAK_FP32_TFLOPS, 5), "traffic": traffic,
+                "traffic_source": traffic_src, "avg_launch_us": round(dom["avg_launch_us"], 3),
+                "flop_per_launch": round(dom["flop_per_launch"]), "launches_timed": dom["launches_per_step"] * reps}
 
     # ---- time-to-PSNR: sketched vs full-gradient PnP-FISTA vs full-resolution PnP-SGD
     ttp = None

@@ -92,6 +92,8 @@ typedef struct fb_stage_info {
     int64_t samples_all_views;
 } fb_stage_info;
 fb_status fb_plan_stage_info(const fb_plan* plan, int stage, fb_stage_info* out);
+/* The same sample count per view: out is a host array of n_views entries. */
+fb_status fb_plan_view_samples(const fb_plan* plan, int stage, int64_t* out);
 
 /*
  * Forward projection y = M A_s x (Sec. 1, Eq. (1); Sec. 2.1, Eq. (4)).
@@ -150,6 +152,12 @@ fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_
  * the next call may then set prepared = 1 to skip its own pooling, which is
  * valid only if it uses that stage and its y_prev is this call's y_out. Use
  * next_stage = -1 and prepared = 0 for independent calls.
+ * events (optional, may be NULL): six hipEvent_t created with timing enabled;
+ * [0], [1] are recorded at the start and completion of the step's
+ * forward-projection kernel, [2], [3] of its back-projection kernel and [4], [5]
+ * of its denoiser kernel (hipExtLaunchKernelGGL start/stop events), so their
+ * elapsed time is the kernel's own duration. A NULL entry is skipped. The
+ * caller owns the events. fb_graph_create ignores them.
  */
 typedef struct fb_pnp_args {
     int32_t stage;
@@ -166,6 +174,7 @@ typedef struct fb_pnp_args {
     float* history;
     int32_t next_stage;
     int32_t prepared;
+    hipEvent_t const* events;
 } fb_pnp_args;
 fb_status pnp_step(const fb_plan* plan, const fb_pnp_args* args, hipStream_t stream);
 

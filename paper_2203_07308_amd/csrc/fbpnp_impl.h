@@ -42,6 +42,7 @@ struct alignas(16) ViewRec {
 struct Stage {
     int f = 1, nxs = 0, nys = 0;
     int64_t samples = 0;            // in-grid samples over all views
+    std::vector<int64_t> view_samples;  // in-grid samples of each view
     RayRec* rays = nullptr;         // device [n_views][n_bins]
     ViewRec* vrec = nullptr;        // device [n_views]
     int pitch_x = 0, pitch_y = 0;   // line pitches of the two line images
@@ -70,7 +71,7 @@ fb_status hip_fail(hipError_t e, const char* what);
 
 // Host plan construction (double precision tables), in plan.cpp.
 fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays, std::vector<ViewRec>& views,
-                             int64_t& samples);
+                             std::vector<int64_t>& view_samples);
 fb_status validate_geometry(const fb_geom& g);
 
 // ---- launch helpers (kernels.hip), used by the forward and reverse entry points
@@ -79,6 +80,20 @@ constexpr int kTvMaxFused = 8;   // TV steps one launch can hold
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 fb_status check_launch(const char* what);
+
+// Timing events for the next projector / denoiser launch of this thread: when
+// set, the launch helpers start their kernel with hipExtLaunchKernelGGL, which
+// records begin at the kernel's start and end at its completion.
+struct LaunchEvents {
+    hipEvent_t begin = nullptr, end = nullptr;
+};
+extern thread_local LaunchEvents t_launch_events;
+struct TimedLaunch {  // scoped: events ev[i], ev[i + 1] (ev may be NULL)
+    TimedLaunch(hipEvent_t const* ev, int i) {
+        if (ev) t_launch_events = {ev[i], ev[i + 1]};
+    }
+    ~TimedLaunch() { t_launch_events = LaunchEvents(); }
+};
 fb_status check_stage(const fb_plan* p, int stage);
 fb_status check_views(const fb_plan* p, const int32_t* views, int n_sel);
 

@@ -11,6 +11,7 @@
 // None of these paths is a dense contraction, so no MFMA is used; the
 // projectors gather and interpolate through the L1/L2 caches, laid out so that
 // the 64 lanes of a wavefront touch consecutive addresses.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -577,6 +578,18 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ w, 
 // ---------------------------------------------------------------------------
 namespace fbpnp {
 
+thread_local LaunchEvents t_launch_events;
+
+// kernel launch on stream S, through hipExtLaunchKernelGGL when timing events are set
+#define FB_LAUNCH(K, G, B, S, ...)                                                                   \
+    do {                                                                                             \
+        const LaunchEvents ev_ = t_launch_events;                                                    \
+        if (ev_.begin || ev_.end)                                                                    \
+            hipExtLaunchKernelGGL(K, G, B, 0, S, ev_.begin, ev_.end, 0, __VA_ARGS__);                \
+        else                                                                                         \
+            K<<<G, B, 0, S>>>(__VA_ARGS__);                                                          \
+    } while (0)
+
 fb_status check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, what);
@@ -628,9 +641,9 @@ fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* view
     const int rays_per_wave = 64 / seg;
     const int bp = cdiv(nb, rays_per_wave) * rays_per_wave;
     const int blocks = cdiv(n_sel * (bp / rays_per_wave), 4);
-#define FB_FP(RES, SG)                                                                                      \
-    k_fp<RES, SG><<<blocks, 256, 0, s>>>(st.rays, nb, bp, views, n_sel, p->g.n_views, L.lx, L.ly_off, L.bytes,  \
-                                         st.pitch_x, st.pitch_y, st.nxs, st.nys, b, y)
+#define FB_FP(RES, SG)                                                                                        \
+    FB_LAUNCH((k_fp<RES, SG>), dim3(blocks), dim3(256), s, st.rays, nb, bp, views, n_sel, p->g.n_views, L.lx,   \
+              L.ly_off, L.bytes, st.pitch_x, st.pitch_y, st.nxs, st.nys, b, y)
     if (resid) {
         if (seg == 4) FB_FP(true, 4);
         else if (seg == 2) FB_FP(true, 2);
@@ -659,9 +672,9 @@ static fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const 
     int vg = 1;
     while (vg < vg_max && nblk * vg < 8192 && vg * 2 <= n_sel) vg *= 2;
     const int nb = p->g.n_bins, f = st.f, nx = p->g.nx;
-#define FB_BP(VG, PX)                                                                                       \
-    k_bp<VG, PX, kFused><<<nblk, 64 * VG, 0, s>>>(st.rays, st.vrec, nb, views, n_sel, p->g.n_views, y, st.nxs, \
-                                                  st.nys, bxs, scale, xo, f, nx, yprev, z)
+#define FB_BP(VG, PX)                                                                                         \
+    FB_LAUNCH((k_bp<VG, PX, kFused>), dim3(nblk), dim3(64 * VG), s, st.rays, st.vrec, nb, views, n_sel,         \
+              p->g.n_views, y, st.nxs, st.nys, bxs, scale, xo, f, nx, yprev, z)
 #define FB_BP_VG(PX)           \
     switch (vg) {              \
         case 1: FB_BP(1, PX); break;  \
@@ -700,9 +713,9 @@ fb_status launch_tv_single(const float* z, int nx, int ny, float lam, float tau,
     const int T = small ? 16 : 32;
     if (pt.f > 0 && T % pt.f != 0) return fail(FB_EINVAL, "pooling factor does not divide the TV tile");
     dim3 grid(cdiv(nx, T), cdiv(ny, T));
-#define FB_TV(TT, HH, NT)                                                                                      \
-    k_tv<TT, HH, NT><<<grid, NT, 0, s>>>(z, nx, ny, lam, tau, n_iter, p_in, p_out, mode, alpha, a_t, x_prev, x_out, \
-                                         y_out, hist, pt.f, pt.inv, pt.lx, pt.px, pt.ly, pt.py, pt.nxs, pt.nys)
+#define FB_TV(TT, HH, NT)                                                                                     \
+    FB_LAUNCH((k_tv<TT, HH, NT>), grid, dim3(NT), s, z, nx, ny, lam, tau, n_iter, p_in, p_out, mode, alpha, a_t, \
+              x_prev, x_out, y_out, hist, pt.f, pt.inv, pt.lx, pt.px, pt.ly, pt.py, pt.nxs, pt.nys)
     if (small) {
         if (n_iter <= 5) FB_TV(16, 6, 256);
         else FB_TV(16, kTvMaxFused + 1, 256);
@@ -748,8 +761,9 @@ fb_status fb_plan_create(const fb_geom* geom, int n_stages, const int32_t* facto
         S.pitch_y = ((S.nxs + 2 * kPad + 3) / 4) * 4;
         std::vector<RayRec> rays;
         std::vector<ViewRec> vr;
-        st = build_stage_tables(*geom, S.f, rays, vr, S.samples);
+        st = build_stage_tables(*geom, S.f, rays, vr, S.view_samples);
         if (st != FB_OK) return cleanup(st);
+        for (int64_t n : S.view_samples) S.samples += n;
         if (hipMalloc(&S.rays, rays.size() * sizeof(RayRec)) != hipSuccess ||
             hipMalloc(&S.vrec, vr.size() * sizeof(ViewRec)) != hipSuccess) {
             p->stages.push_back(S);
@@ -800,6 +814,15 @@ fb_status fb_plan_stage_info(const fb_plan* p, int stage, fb_stage_info* out) {
     out->nxs = S.nxs;
     out->nys = S.nys;
     out->samples_all_views = S.samples;
+    return FB_OK;
+}
+
+fb_status fb_plan_view_samples(const fb_plan* p, int stage, int64_t* out) {
+    fb_status st = check_stage(p, stage);
+    if (st != FB_OK) return st;
+    if (!out) return fail(FB_EINVAL, "out is NULL");
+    const Stage& S = p->stages[stage];
+    std::copy(S.view_samples.begin(), S.view_samples.end(), out);
     return FB_OK;
 }
 
@@ -890,11 +913,17 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
     const Stage& S = p->stages[a->stage];
     const int nx = p->g.nx, ny = p->g.ny;
     if (!a->prepared && (st = launch_prepare(p, a->stage, a->y_prev, nx, S.f, stream)) != FB_OK) return st;
-    if ((st = launch_fp(p, a->stage, true, a->views, a->n_sel, a->b, p->resid, stream)) != FB_OK) return st;
+    {
+        TimedLaunch tl(a->events, 0);
+        if ((st = launch_fp(p, a->stage, true, a->views, a->n_sel, a->b, p->resid, stream)) != FB_OK) return st;
+    }
     const float step = a->eta * a->sigma / (float)(S.f * S.f);
-    if ((st = launch_bp_t<true>(p, a->stage, p->resid, a->views, a->n_sel, step, nullptr, a->y_prev, p->zbuf,
-                                stream)) != FB_OK)
-        return st;
+    {
+        TimedLaunch tl(a->events, 2);
+        if ((st = launch_bp_t<true>(p, a->stage, p->resid, a->views, a->n_sel, step, nullptr, a->y_prev, p->zbuf,
+                                    stream)) != FB_OK)
+            return st;
+    }
     PoolTarget pt;
     if (a->next_stage >= 0) {
         const Stage& N = p->stages[a->next_stage];
@@ -912,6 +941,7 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
     // only applies the relaxation and momentum (div p = 0)
     const float lam = a->lambda > 0.f ? a->lambda : 1.f;
     const int iters = a->lambda > 0.f ? a->tv_iters : 0;
+    TimedLaunch tl(a->events, 4);
     return launch_tv_single(p->zbuf, nx, ny, lam, a->tau, iters, nullptr, nullptr, 1, a->alpha, a->a_t, a->x_prev,
                             a->x_out, a->y_out, a->history, stream, pt);
 }
@@ -938,6 +968,7 @@ fb_status fb_graph_create(const fb_plan* p, const fb_pnp_args* steps, int n_step
     for (int i = 0; i < n_steps; ++i) {
         chain[i].prepared = 0;
         chain[i].next_stage = -1;
+        chain[i].events = nullptr;  // kernel timing is for direct calls only
     }
     for (int i = 0; i + 1 < n_steps; ++i) {
         if (chain[i + 1].y_prev == chain[i].y_out && chain[i + 1].stage >= 0 &&

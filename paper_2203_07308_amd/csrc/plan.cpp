@@ -83,13 +83,13 @@ static void valid_range(double p0, double dp, int nlines, double pmin, double pm
 }
 
 fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays, std::vector<ViewRec>& views,
-                             int64_t& samples) {
+                             std::vector<int64_t>& view_samples) {
     const int nxs = g.nx / f, nys = g.ny / f, nb = g.n_bins;
     const double hs = g.pixel_mm * f;
     const double cxs = 0.5 * (nxs - 1), cys = 0.5 * (nys - 1);
     rays.assign((size_t)g.n_views * nb, RayRec{0.f, 0.f, 0.f, 0u});
     views.assign(g.n_views, ViewRec{});
-    samples = 0;
+    view_samples.assign(g.n_views, 0);
     for (int k = 0; k < g.n_views; ++k) {
         const double beta = g.angle0_rad + (double)k * g.angle_step_rad;
         const double cb = std::cos(beta), sb = std::sin(beta);
@@ -150,7 +150,7 @@ fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays,
                 r.dpos = dpf;
                 r.len = (float)w;
                 r.bits = (uint32_t)lo | ((uint32_t)n << 16) | (xmajor ? 0u : 0x80000000u);
-                samples += n;
+                view_samples[k] += n;
             } else {
                 r.pos_c = 0.f;
                 r.dpos = 0.f;

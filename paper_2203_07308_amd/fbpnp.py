@@ -24,7 +24,7 @@ EXPORTS = [
     "fb_last_error", "fb_plan_create", "fb_plan_destroy", "fb_plan_stage_info", "fanbeam_fp", "fanbeam_bp",
     "sketch_down", "sketch_up", "fb_tv_workspace_bytes", "tv_prox", "pnp_step", "fb_graph_create",
     "fb_graph_launch", "fb_graph_destroy", "fb_tv_vjp_workspace_bytes", "tv_prox_vjp",
-    "fb_pnp_vjp_workspace_bytes", "pnp_step_vjp", "fb_power_lipschitz",
+    "fb_pnp_vjp_workspace_bytes", "pnp_step_vjp", "fb_power_lipschitz", "fb_plan_view_samples",
 ]
 
 
@@ -57,6 +57,7 @@ class PnpArgs(ctypes.Structure):
         ("b", ctypes.c_void_p), ("y_prev", ctypes.c_void_p), ("x_prev", ctypes.c_void_p),
         ("x_out", ctypes.c_void_p), ("y_out", ctypes.c_void_p), ("history", ctypes.c_void_p),
         ("next_stage", ctypes.c_int32), ("prepared", ctypes.c_int32),
+        ("events", ctypes.POINTER(ctypes.c_void_p)),
     ]
 
 
@@ -89,6 +90,7 @@ def load() -> ctypes.CDLL:
     lib.fb_graph_create.argtypes = [vp, P(PnpArgs), c_int, P(vp)]
     lib.fb_graph_launch.argtypes = [vp, vp]
     lib.fb_graph_destroy.argtypes = [vp]
+    lib.fb_plan_view_samples.argtypes = [vp, c_int, P(ctypes.c_int64)]
     lib.fb_power_lipschitz.argtypes = [vp, c_int, c_int, P(ctypes.c_double), vp]
     lib.fb_tv_vjp_workspace_bytes.argtypes = [c_int, c_int, c_int]
     lib.fb_tv_vjp_workspace_bytes.restype = ctypes.c_size_t
@@ -180,6 +182,12 @@ class Plan:
         _check(load().fb_plan_stage_info(self._h, stage, ctypes.byref(out)))
         return out
 
+    def view_samples(self, stage: int):
+        """In-grid Joseph samples of each view at this stage (host list of n_views ints)."""
+        out = (ctypes.c_int64 * self.geom.n_views)()
+        _check(load().fb_plan_view_samples(self._h, stage, out))
+        return list(out)
+
     def coarse_shape(self, stage: int):
         f = self.factors[stage]
         return (self.geom.ny // f, self.geom.nx // f)
@@ -241,14 +249,41 @@ def tv_prox(z: torch.Tensor, x: torch.Tensor, lam: float, n_iter: int = 5, tau: 
 
 def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float, a_t: float,
              views: torch.Tensor | None = None, sigma: float = 1.0, alpha: float = 1.0, lam: float = 0.01,
-             tau: float = 0.125, tv_iters: int = 5, history: torch.Tensor | None = None) -> PnpArgs:
+             tau: float = 0.125, tv_iters: int = 5, history: torch.Tensor | None = None,
+             events=None) -> PnpArgs:
+    """Arguments of one pnp_step. events: optional sequence of six torch.cuda.Event
+    (enable_timing=True) or None, recorded around the step's fp, bp and TV kernels."""
     npix = plan.geom.nx * plan.geom.ny
     vp, n_sel = _views(plan, views)
-    return PnpArgs(stage, vp, n_sel, sigma, eta, alpha, a_t, lam, tau, tv_iters,
-                   _ptr(b, numel=plan.geom.n_views * plan.geom.n_bins, name="b"),
-                   _ptr(y_prev, numel=npix, name="y_prev"), _ptr(x_prev, numel=npix, name="x_prev"),
-                   _ptr(x_out, numel=npix, name="x_out"), _ptr(y_out, numel=npix, name="y_out"),
-                   _ptr(history, numel=npix, name="history"), -1, 0)
+    a = PnpArgs(stage, vp, n_sel, sigma, eta, alpha, a_t, lam, tau, tv_iters,
+                _ptr(b, numel=plan.geom.n_views * plan.geom.n_bins, name="b"),
+                _ptr(y_prev, numel=npix, name="y_prev"), _ptr(x_prev, numel=npix, name="x_prev"),
+                _ptr(x_out, numel=npix, name="x_out"), _ptr(y_out, numel=npix, name="y_out"),
+                _ptr(history, numel=npix, name="history"), -1, 0)
+    if events is not None:
+        if len(events) != 6:
+            raise ValueError("events: need six entries (fp, bp, TV; begin and end)")
+        handles = []
+        for ev in events:
+            if ev is None:
+                handles.append(None)
+                continue
+            if not ev.cuda_event:  # torch creates the event on its first record
+                ev.record()
+            handles.append(ev.cuda_event)
+        a.events = (ctypes.c_void_p * 6)(*handles)  # the struct keeps the array alive
+    return a
+
+
+def chain_steps(steps) -> None:
+    """Sets next_stage / prepared on consecutive step arguments the way fb_graph_create
+    does (step i pools y_t for step i + 1 when that step reads it), for a schedule run
+    by direct pnp_step calls in this order."""
+    for a in steps:
+        a.next_stage, a.prepared = -1, 0
+    for a, b in zip(steps[:-1], steps[1:]):
+        if b.y_prev == a.y_out:
+            a.next_stage, b.prepared = b.stage, 1
 
 
 def pnp_step(plan: Plan, args: PnpArgs, stream=None) -> None:

@@ -1,0 +1,45 @@
+"""Host-side logic of bench.py: labelling of profiled dispatches by iteration group and
+reading of the committed HBM-traffic summary (no GPU)."""
+import os
+
+import bench
+
+
+def schedule_names(n_replays=2):
+    names = ["fill", "fill"]
+    for _ in range(n_replays):
+        names.append("k_prepare")
+        for t in range(60):
+            f = (4, 2, 1)[t // 20]
+            names += ["k_fp<true, 4>", f"k_bp<{16 if f > 1 else 8}, {1 if f == 4 else 2}, true>", "k_tv<32, 6, 1024>"]
+        names += ["fill", "fill"]
+    names.append("__amd_rocclr_copyBuffer")
+    return names
+
+
+def test_label_dispatches_groups_every_replay():
+    names = schedule_names(2)
+    lab = bench.label_dispatches(names)
+    groups = {}
+    for g, j in lab:
+        groups.setdefault(g, []).append(j)
+    assert groups["prepare_f4"] == [2, 2 + 181 + 2]
+    for c in ("fp", "bp", "tv"):
+        for f in (4, 2, 1):
+            js = groups[f"{c}_f{f}"]
+            assert len(js) == 40
+            assert all(names[j].startswith("k_" + c) for j in js)
+    # a truncated replay is not counted
+    lab2 = bench.label_dispatches(names[: 2 + 181 + 2 + 100])
+    assert len(lab2) == 181
+
+
+def test_launch_traffic_reads_matching_summary(tmp_path):
+    p = tmp_path / "t.md"
+    row = "| bp_f1 | `k_bp<8, 2, true>` | 40 | 5210.4 | 1024.0 | 10666042 | 1048576 | 11714618 |"
+    p.write_text(f"kernel sources sha256: `{bench.kernel_source_hash()}`\n\n{row}\n")
+    assert bench.launch_traffic("bp_f1", str(p))[0] == 11714618
+    assert bench.launch_traffic("fp_f1", str(p))[0] is None
+    p.write_text(f"kernel sources sha256: `{'0' * 64}`\n\n{row}\n")
+    assert bench.launch_traffic("bp_f1", str(p))[0] is None
+    assert bench.launch_traffic("bp_f1", os.path.join(str(tmp_path), "missing.md"))[0] is None

@@ -159,6 +159,11 @@ def test_stage_sample_counts_match_oracle():
         assert (info.factor, info.nxs, info.nys) == (f, 256 // f, 256 // f)
         ref = oracle.count_samples(og, f)
         assert abs(info.samples_all_views - ref) <= 1e-6 * ref
+        per_view = plan.view_samples(s)
+        assert sum(per_view) == info.samples_all_views
+        for k in (0, 17, 100, gd["n_views"] - 1):
+            rk = oracle.count_samples(og, f, np.array([k], dtype=np.int32))
+            assert abs(per_view[k] - rk) <= 2 + 1e-5 * rk, (f, k, per_view[k], rk)
 
 
 @pytest.mark.parametrize("shape,f", [((64, 64), 1), ((64, 64), 2), ((512, 512), 4), ((48, 80), 4), ((30, 42), 3)])
@@ -198,8 +203,11 @@ def problem(name, seed=0):
     return w, gd, og, xt, b
 
 
-def run_gpu(plan, gd, b, sched, eta, a, alpha=1.0, lam=0.01, history=False, graph=False):
-    """Runs the schedule with pnp_step (or as one captured graph). sched: (stage_index, views, sigma)."""
+def run_gpu(plan, gd, b, sched, eta, a, alpha=1.0, lam=0.01, history=False, graph=False, chained=False,
+            events=None):
+    """Runs the schedule with pnp_step (or as one captured graph). sched: (stage_index, views, sigma).
+    chained: direct calls with the graph's pooling hand-over; events: list that receives six
+    timing events per step."""
     npix = gd["nx"] * gd["ny"]
     bd = dev(b)
     xb = torch.zeros(npix, device="cuda")
@@ -210,8 +218,14 @@ def run_gpu(plan, gd, b, sched, eta, a, alpha=1.0, lam=0.01, history=False, grap
     for t, (s, views, sigma) in enumerate(sched):
         dv = None if views is None else dev(views, np.int32)
         keep.append(dv)
+        ev = None
+        if events is not None:
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+            events.append(ev)
         steps.append(fbpnp.pnp_args(plan, s, bd, yb, xb, xb, yb, float(eta[t]), float(a[t]), dv, sigma,
-                                    alpha, lam, 0.125, 5, None if hist is None else hist[t]))
+                                    alpha, lam, 0.125, 5, None if hist is None else hist[t], ev))
+    if chained:
+        fbpnp.chain_steps(steps)
     if graph:
         g = fbpnp.Graph(plan, steps)
         g.launch()
@@ -303,6 +317,15 @@ def test_graph_replay_equals_eager_and_is_deterministic():
     g1 = run_gpu(plan, gd, b, sched, eta, a, graph=True)
     np.testing.assert_array_equal(e1, e2)
     np.testing.assert_array_equal(e1, g1)
+    # direct calls with the graph's pooling hand-over and kernel timing events: same bits
+    evs = []
+    c1 = run_gpu(plan, gd, b, sched, eta, a, chained=True, events=evs)
+    np.testing.assert_array_equal(e1, c1)
+    torch.cuda.synchronize()
+    for ev in evs:
+        for k in (0, 2, 4):
+            ms = ev[k].elapsed_time(ev[k + 1])
+            assert 0.0 < ms < 50.0, ms
 
 
 def test_power_lipschitz_matches_oracle():
