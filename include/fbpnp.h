@@ -96,6 +96,27 @@ fb_status fb_plan_stage_info(const fb_plan* plan, int stage, fb_stage_info* out)
 fb_status fb_plan_view_samples(const fb_plan* plan, int stage, int64_t* out);
 
 /*
+ * Launch configuration of a stage's kernels (no effect on what is computed,
+ * only on how the work is split; results can differ in the last bits where
+ * the split changes a summation order):
+ *   fp_seg   lanes per ray in the forward projector (1, 2 or 4; a wavefront
+ *            holds 64 / fp_seg rays, a work-group 256 / fp_seg)
+ *   bp_px    pixels per lane side in the backprojector (1, 2 or 4; a
+ *            wavefront owns an 8 bp_px square)
+ *   bp_vg    wavefronts per work-group splitting the views (1..16, <= 4 when
+ *            bp_px = 4)
+ *   tv_tile  TV-prox output tile side (16 or 32)
+ * A zero field selects the built-in default for the call's size.
+ * fb_plan_set_config: cfg NULL restores every default.
+ * fb_plan_get_config: the configuration calls with n_sel views use.
+ */
+typedef struct fb_launch_config {
+    int32_t fp_seg, bp_px, bp_vg, tv_tile;
+} fb_launch_config;
+fb_status fb_plan_set_config(fb_plan* plan, int stage, const fb_launch_config* cfg);
+fb_status fb_plan_get_config(const fb_plan* plan, int stage, int n_sel, fb_launch_config* out);
+
+/*
  * Forward projection y = M A_s x (Sec. 1, Eq. (1); Sec. 2.1, Eq. (4)).
  *   x: device [nys][nxs] image on the stage's coarse grid.
  *   views: device int32 list of n_sel view indices (the rows of M), or NULL
@@ -187,6 +208,73 @@ typedef struct fb_graph fb_graph;
 fb_status fb_graph_create(const fb_plan* plan, const fb_pnp_args* steps, int n_steps, fb_graph** out);
 fb_status fb_graph_launch(fb_graph* graph, hipStream_t stream);
 fb_status fb_graph_destroy(fb_graph* graph);
+
+/*
+ * Batched form: many independent slices (own geometry, size, views and
+ * detector; shared stage factors) advanced together, each kernel of an
+ * iteration issued once for the whole batch, with work-groups ordered
+ * longest-processing-time first across slices.
+ *   fb_batch_create: one plan per slice (geoms[n_slices]; every factor must
+ *     divide every slice's nx and ny; 1..4 stages, at most 4096 slices).
+ *   fb_batch_layout: the caller's arenas. image_offsets and sino_offsets are
+ *     host arrays of n_slices + 1 entries receiving each slice's offset in
+ *     floats (256-byte aligned) and, last, the arena size: slice s's image
+ *     [ny][nx] starts at image_offsets[s], its sinogram [n_views][n_bins] at
+ *     sino_offsets[s].
+ *   fb_batch_slice_plan: the plan the batch holds for one slice (owned by the
+ *     batch; it shares that plan's workspace, so do not use it concurrently
+ *     with batched calls).
+ *   pnp_step_batched: one iteration of Algorithm 1 for every slice, as
+ *     pnp_step, on the arenas. eta is a device array [n_slices] of per-slice
+ *     step sizes. n_sub <= 1 selects all views; n_sub > 1 selects views
+ *     k = subset + n_sub i of every slice (the gradient is then usually scaled
+ *     by sigma = n_sub). history (optional) is an image arena receiving x_t.
+ *     next_stage / prepared / events as in fb_pnp_args. A step's work lists
+ *     are built on its first use, which cannot happen under stream capture:
+ *     capture with fb_batch_graph_create, which builds them first.
+ *   fb_batch_set_config / fb_batch_get_config: launch configuration per
+ *     stage, as for plans (get: the one used with n_sub subsets).
+ */
+typedef struct fb_batch fb_batch;
+typedef struct fb_batch_args {
+    int32_t stage;
+    int32_t n_sub, subset;
+    float sigma, alpha, a_t;
+    float lambda, tau;
+    int32_t tv_iters;
+    const float* eta;
+    const float* b;
+    const float* y_prev;
+    const float* x_prev;
+    float* x_out;
+    float* y_out;
+    float* history;
+    int32_t next_stage;
+    int32_t prepared;
+    hipEvent_t const* events;
+} fb_batch_args;
+fb_status fb_batch_create(const fb_geom* geoms, int n_slices, int n_stages, const int32_t* factors, fb_batch** out);
+fb_status fb_batch_destroy(fb_batch* batch);
+fb_status fb_batch_layout(const fb_batch* batch, int64_t* image_offsets, int64_t* sino_offsets);
+fb_status fb_batch_slice_plan(fb_batch* batch, int slice, fb_plan** out);
+fb_status fb_batch_set_config(fb_batch* batch, int stage, const fb_launch_config* cfg);
+fb_status fb_batch_get_config(const fb_batch* batch, int stage, int n_sub, fb_launch_config* out);
+fb_status pnp_step_batched(fb_batch* batch, const fb_batch_args* args, hipStream_t stream);
+fb_status fb_batch_graph_create(fb_batch* batch, const fb_batch_args* steps, int n_steps, fb_graph** out);
+
+/*
+ * Autotuner: for every stage, times each launch configuration candidate on
+ * synthetic data of the stage's shape (HIP events on the stream), keeps the
+ * fastest whose output agrees with the default configuration's within 1e-5
+ * relative L2, and sets it on the plan (calls with n_sel views) or the batch
+ * (steps with n_sub subsets). Allocates temporary device memory and
+ * synchronises the stream: a set-up call. cache_path (optional) is a text
+ * file of earlier results, read first and appended to; a cached entry for the
+ * same device, geometry, stage and view selection is used without timing. On
+ * error the configuration is left as it was.
+ */
+fb_status fb_autotune(fb_plan* plan, int n_sel, const char* cache_path, hipStream_t stream);
+fb_status fb_batch_autotune(fb_batch* batch, int n_sub, const char* cache_path, hipStream_t stream);
 
 /*
  * Reverse mode (differentiation of unrolled iterations).

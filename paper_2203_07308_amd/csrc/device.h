@@ -1,0 +1,512 @@
+// Device bodies of the hot-path kernels, shared by the single-image kernels
+// (kernels.hip) and the batched ones (batch.hip). Each body computes one
+// work-group's share given its block index, so a batched kernel maps its block
+// to (slice, block) and calls the same code with that slice's tables.
+//
+// Hot path of one PnP-MS2G iteration (Sec. 2.1, Algorithm 1 with the
+// least-squares data term of Eq. (5)-(7)):
+//   prepare_body  pooling S = D_f of y_{t-1} into the stage's two "line images"
+//   fp_body       Joseph forward projection of the selected views, minus b
+//   bp_body       matched backprojection as a pixel-driven gather, fused with
+//                 the upsampler U = D_f^T and the gradient step z = y - eta U G
+//   tv_body       Chambolle TV-prox iterations in LDS, fused with the
+//                 relaxation and the momentum step
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fbpnp_impl.h"
+
+namespace fbpnp {
+namespace dev {
+
+// ---------------------------------------------------------------------------
+// Line images: the stage image v (ny_s x nx_s) stored twice, as
+//   lx[c][kPad + r] = v[r][c]   (lines = columns, used by x-major rays)
+//   ly[r][kPad + c] = v[r][c]   (lines = rows, used by y-major rays)
+// with kPad zeros at both ends of every line (written once at plan creation).
+// Along a line, the rays of one view that a wavefront handles sample nearby
+// positions, so their two interpolation taps are contiguous loads.
+// ---------------------------------------------------------------------------
+constexpr int kTile = 32;
+
+// v = D_f x (x: ny x nx, full grid; f = 1 copies), written into both line images.
+__device__ __forceinline__ void prepare_body(int bx, int by, const float* __restrict__ x, int nx, int f,
+                                             float inv_ff, int nxs, int nys, float* __restrict__ lx, int pitch_x,
+                                             float* __restrict__ ly, int pitch_y) {
+    __shared__ float tile[kTile][kTile + 1];
+    const int C0 = bx * kTile, R0 = by * kTile;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int rr = ty; rr < kTile; rr += 8) {
+        const int R = R0 + rr, C = C0 + tx;
+        float s = 0.f;
+        if (R < nys && C < nxs) {
+            if (f == 1) {
+                s = x[(size_t)R * nx + C];
+            } else {
+                for (int a = 0; a < f; ++a) {
+                    const float* row = x + (size_t)(f * R + a) * nx + (size_t)f * C;
+                    for (int b = 0; b < f; ++b) s += row[b];
+                }
+                s *= inv_ff;
+            }
+            ly[(size_t)R * pitch_y + kPad + C] = s;
+        }
+        tile[rr][tx] = s;
+    }
+    __syncthreads();
+    for (int cc = ty; cc < kTile; cc += 8) {
+        const int C = C0 + cc, R = R0 + tx;
+        if (R < nys && C < nxs) lx[(size_t)C * pitch_x + kPad + R] = tile[tx][cc];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward projection: SEG work-items per (selected view, bin), each marching
+// a contiguous share of the ray's samples (SEG > 1 when there are too few rays
+// to fill the GPU). The 64/SEG rays of a wavefront are consecutive bins of
+// one view, so the ray-table read is coalesced and the taps fall on
+// neighbouring positions of the same line.
+//   y[i][j] = len_j * sum_k [ (1-w) v(line lo+k, p0) + w v(line lo+k, p0+1) ]
+//             (- b[view_i][j] when kResid)
+// with p = npos/2 + fma(lo + k - nlines/2, dpos, pos_c), p0 = floor(p),
+// w = fract(p) (zero outside the grid).
+// ---------------------------------------------------------------------------
+// Buffer resource word 3 for raw (untyped) buffer loads on CDNA.
+constexpr int kBufWord3 = 0x00020000;
+
+// Wavefront-wide minimum and maximum (every lane gets the result).
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Work-group blk (256 threads) of a projection; view i of the selection is
+// views[i], or view0 + i * view_step without a list.
+template <bool kResid, int SEG>
+__device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays, int n_bins, int bins_padded,
+                                        const int32_t* __restrict__ views, int view0, int view_step, int n_sel,
+                                        int n_views, const float* __restrict__ lines, int ly_off, int line_bytes,
+                                        int pitch_x, int pitch_y, int nxs, int nys, const float* __restrict__ b,
+                                        float* __restrict__ y) {
+    constexpr int R = 64 / SEG;  // rays per wavefront; SEG lanes share one ray
+    const int lane = threadIdx.x & 63;
+    const int wave = (blk * 256 + (int)threadIdx.x) >> 6;
+    const int waves_per_view = bins_padded / R;
+    const int i = wave / waves_per_view;
+    const int j = (wave - i * waves_per_view) * R + lane % R;
+    const int seg = lane / R;
+    const bool active = i < n_sel && j < n_bins;
+    // both line images of the stage as one buffer: 32-bit offsets, and a load
+    // outside it would return zero instead of faulting
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(lines), (short)0, line_bytes, kBufWord3);
+    int v = 0;
+    if (active) v = views ? views[i] : view0 + i * view_step;
+    const bool valid = active && (unsigned)v < (unsigned)n_views;  // invalid view index: a zero row
+    RayRec r{0.f, 0.f, 0.f, 0u};
+    if (valid) r = rays[(size_t)v * n_bins + j];
+    const int lo = (int)(r.bits & 0xFFFFu), n = (int)((r.bits >> 16) & 0x7FFFu);
+    const bool ymaj = (r.bits >> 31) != 0u;
+    if (n == 0) {  // no samples (or no ray): every position clamps into the padding
+        r.pos_c = -1e30f;
+        r.dpos = 0.f;
+    }
+    // All lanes march the same lines in lockstep (the union of the wavefront's
+    // sample ranges, split into SEG parts), so one load instruction reads
+    // neighbouring positions of one line. Outside its own range a ray's
+    // position is clamped into the zero padding and adds nothing.
+    const int L0 = wave_min(n > 0 ? lo : 1 << 30), L1 = wave_max(n > 0 ? lo + n : -(1 << 30));
+    float acc = 0.f;
+    if (L1 > L0) {
+        const int la = L0 + ((L1 - L0) * seg) / SEG, lb = L0 + ((L1 - L0) * (seg + 1)) / SEG;
+        const int pitch = ymaj ? pitch_y : pitch_x;
+        const int npos = ymaj ? nxs : nys;
+        const int mid = npos >> 1, lmid = (ymaj ? nys : nxs) >> 1;
+        const float plo = (float)(-2 - mid), phi = (float)(npos - mid);
+        // byte offset of position mid on line la
+        int off = ((ymaj ? ly_off : 0) + la * pitch + kPad + mid) * 4;
+        const int step = pitch * 4;
+        float kf = (float)(la - lmid);
+#pragma unroll 4
+        for (int l = la; l < lb; ++l) {
+            const float p = __builtin_amdgcn_fmed3f(fmaf(kf, r.dpos, r.pos_c), plo, phi);
+            const float w = __builtin_amdgcn_fractf(p);
+            const int i0 = (int)floorf(p);
+            const auto t = __builtin_amdgcn_raw_buffer_load_b64(rsrc, off + i0 * 4, 0, 0);
+            const float a = __uint_as_float(t[0]), c = __uint_as_float(t[1]);
+            acc += fmaf(w, c - a, a);
+            kf += 1.f;
+            off += step;
+        }
+    }
+    // fixed-order sum of the SEG partial sums of each ray
+#pragma unroll
+    for (int o = R; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
+    if (active && seg == 0) {
+        float val = 0.f;
+        if (valid) {
+            val = acc * r.len;
+            if (kResid) val -= b[(size_t)v * n_bins + j];
+        }
+        y[(size_t)i * n_bins + j] = val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Matched backprojection, pixel-driven gather.
+//
+// A wavefront owns a block of 8 PX x 8 PX stage pixels, each lane a PX x PX
+// block. For every selected view the wavefront first copies the ray records
+// of the bins its block can touch (found from the detector coordinate j(c, r)
+// of the block corners) into its own LDS slot, with y * len folded in. Each
+// lane then finds the rays that can touch its pixels from j(c, r) at the ends
+// of its strips and recomputes every candidate's interpolation weight from
+// the same float position k_fp uses (same operations on the same table
+// entries):
+//   x-major ray, column cc: p = nys/2 + fma(cc - nxs/2, dpos, pos_c),
+//   row floor(p) receives 1 - fract(p) and row floor(p)+1 receives fract(p).
+// A ray without a sample on the strip's line has p outside [-1, npos) there
+// (the plan guarantees it), so it adds nothing.
+// The VG wavefronts of a workgroup share the pixel block and split the views;
+// their partial sums are added in a fixed order in LDS, so results are
+// bitwise reproducible (no atomics).
+// ---------------------------------------------------------------------------
+constexpr float kProjEps = 0.02f;  // margin on candidate bin ranges (FP32 error is ~1e-4 bins)
+constexpr int kStageRays = 128;    // ray records staged per wavefront and view
+
+__device__ __forceinline__ float proj_bin(const ViewRec& v, float c, float r) {
+    const float num = fmaf(v.a2, r, fmaf(v.a1, c, v.a0));
+    const float den = fmaf(v.b2, r, fmaf(v.b1, c, v.b0));
+    return fmaf(num, __builtin_amdgcn_rcpf(den), v.j0);
+}
+
+__device__ __forceinline__ void cand_range(float j1, float j2, int lo, int hi, int& jl, int& jh) {
+    const float a = fmaxf(ceilf(fminf(j1, j2) - kProjEps), (float)lo);
+    const float b = fminf(floorf(fmaxf(j1, j2) + kProjEps), (float)hi);
+    jl = (int)a;
+    jh = (int)b;
+}
+
+// Adds one sample (centred position p, weighted value yy) to a strip of PX
+// pixels whose first centred position is qf. Pixel qf+t receives the linear
+// interpolation weight max(0, 1 - |p - (qf+t)|): 1 - fract(p) on row floor(p)
+// and fract(p) on row floor(p)+1, as in k_fp (exactly so for |p| >= 1, where
+// every difference involved is representable; within one rounding otherwise).
+template <int PX>
+__device__ __forceinline__ void strip_add(float p, float qf, float yy, float (&s)[PX]) {
+    const float e = p - qf;
+#pragma unroll
+    for (int t = 0; t < PX; ++t) {
+        const float wt = fmaxf(1.f - fabsf(e - (float)t), 0.f);
+        s[t] = fmaf(wt, yy, s[t]);
+    }
+}
+
+// Candidate rays jl..jh (one dominance class, staged from bin base) for a
+// strip on a line whose offset from the middle line is kf, first centred
+// position qm.
+template <int PX>
+__device__ __forceinline__ void gather_strip(const float4* __restrict__ st, int base, int jl, int jh, float kf,
+                                             int qm, float (&s)[PX]) {
+    const float qf = (float)qm;
+    for (int j = jl; j <= jh; ++j) {
+        const float4 e = st[j - base];
+        strip_add<PX>(fmaf(kf, e.y, e.x), qf, e.z, s);
+    }
+}
+
+// All strips of one dominance class for one staged view. The candidate bins
+// of a strip come from j(c, r) at its two ends (the numerator and the
+// denominator of j are linear in c and r); lo..hi is the class range within
+// the staged chunk.
+template <int PX, bool kXMajor>
+__device__ __forceinline__ void bp_class(const ViewRec& vr, const float4* __restrict__ st, int base, int lo,
+                                                   int hi, float cc, float rc, int c, int r, int mid_c, int mid_r,
+                                                   float (&acc)[PX][PX]) {
+    if (lo > hi) return;
+    // x-major: strips are columns c+t over rows r-1 .. r+PX;
+    // y-major: strips are rows r+t over columns c-1 .. c+PX
+    const float n0 = kXMajor ? fmaf(vr.a2, rc - 1.f, fmaf(vr.a1, cc, vr.a0))
+                             : fmaf(vr.a2, rc, fmaf(vr.a1, cc - 1.f, vr.a0));
+    const float d0 = kXMajor ? fmaf(vr.b2, rc - 1.f, fmaf(vr.b1, cc, vr.b0))
+                             : fmaf(vr.b2, rc, fmaf(vr.b1, cc - 1.f, vr.b0));
+    const float an = kXMajor ? vr.a2 : vr.a1, bn = kXMajor ? vr.b2 : vr.b1;  // along the strip
+    const float at = kXMajor ? vr.a1 : vr.a2, bt = kXMajor ? vr.b1 : vr.b2;  // across strips
+    const float dn = an * (float)(PX + 1), dd = bn * (float)(PX + 1);
+#pragma unroll
+    for (int t = 0; t < PX; ++t) {
+        const float nt = fmaf(at, (float)t, n0), dt = fmaf(bt, (float)t, d0);
+        int jl, jh;
+        cand_range(fmaf(nt, __builtin_amdgcn_rcpf(dt), vr.j0), fmaf(nt + dn, __builtin_amdgcn_rcpf(dt + dd), vr.j0),
+                   lo, hi, jl, jh);
+        float sacc[PX];
+#pragma unroll
+        for (int w = 0; w < PX; ++w) sacc[w] = 0.f;
+        if (kXMajor) {
+            gather_strip<PX>(st, base, jl, jh, (float)(c + t - mid_c), r - mid_r, sacc);
+#pragma unroll
+            for (int w = 0; w < PX; ++w) acc[w][t] += sacc[w];
+        } else {
+            gather_strip<PX>(st, base, jl, jh, (float)(r + t - mid_r), c - mid_c, sacc);
+#pragma unroll
+            for (int w = 0; w < PX; ++w) acc[t][w] += sacc[w];
+        }
+    }
+}
+
+// Work-group blk (64 VG threads) of a backprojection; views as in fp_body.
+template <int VG, int PX, bool kFused>
+__device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays, const ViewRec* __restrict__ vrec,
+                                        int n_bins, const int32_t* __restrict__ views, int view0, int view_step,
+                                        int n_sel, int n_views, const float* __restrict__ y, int nxs, int nys,
+                                        int blocks_x, float scale, float* __restrict__ xo, int f, int nx,
+                                        const float* __restrict__ yprev, float* __restrict__ z) {
+    constexpr int BW = 8 * PX;  // block width in pixels
+    __shared__ float4 stage[VG][kStageRays];
+    __shared__ float red[VG > 1 ? VG - 1 : 1][PX * PX][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int bx = blk % blocks_x, by = blk / blocks_x;
+    const int c = bx * BW + PX * (lane & 7), r = by * BW + PX * (lane >> 3);
+    const float hx = 0.5f * (float)(nxs - 1), hy = 0.5f * (float)(nys - 1);
+    const float cc = (float)c - hx, rc = (float)r - hy;
+    // corners of the block grown by the strip ends (one pixel before, one after)
+    const float cb0 = (float)(bx * BW - 1) - hx, cb1 = (float)(bx * BW + BW) - hx;
+    const float rb0 = (float)(by * BW - 1) - hy, rb1 = (float)(by * BW + BW) - hy;
+    const int mid_r = nys >> 1, mid_c = nxs >> 1;
+    float acc[PX][PX];
+#pragma unroll
+    for (int a = 0; a < PX; ++a)
+#pragma unroll
+        for (int b = 0; b < PX; ++b) acc[a][b] = 0.f;
+    float4* st = stage[wave];
+    // this wavefront's views are i = wave + VG t, t < n_mine; lane u first
+    // finds the bin footprint of view t0 + u (block corners grown by the strip
+    // ends), then the wavefront walks those views one by one
+    const int n_mine = n_sel > wave ? (n_sel - wave + VG - 1) / VG : 0;
+    for (int t0 = 0; t0 < n_mine; t0 += 64) {
+        int my_v = -1, my_j0 = 0, my_j1 = -1;
+        if (t0 + lane < n_mine) {
+            const int iu = wave + VG * (t0 + lane);
+            const int vu = views ? views[iu] : view0 + iu * view_step;
+            if ((unsigned)vu < (unsigned)n_views) {  // invalid view index: no contribution
+                const ViewRec vq = vrec[vu];
+                const float q0 = proj_bin(vq, cb0, rb0), q1 = proj_bin(vq, cb1, rb0);
+                const float q2 = proj_bin(vq, cb0, rb1), q3 = proj_bin(vq, cb1, rb1);
+                const float jmin = fminf(fminf(q0, q1), fminf(q2, q3));
+                const float jmax = fmaxf(fmaxf(q0, q1), fmaxf(q2, q3));
+                my_v = vu;
+                my_j0 = (int)fmaxf(floorf(jmin - kProjEps), 0.f);
+                my_j1 = (int)fminf(ceilf(jmax + kProjEps), (float)(n_bins - 1));
+            }
+        }
+        const int tn = min(64, n_mine - t0);
+        for (int u = 0; u < tn; ++u) {
+            const int v = __builtin_amdgcn_readlane(my_v, u);
+            if (v < 0) continue;
+            const int i = wave + VG * (t0 + u);
+            const int j0 = __builtin_amdgcn_readlane(my_j0, u), j1 = __builtin_amdgcn_readlane(my_j1, u);
+            const ViewRec vr = vrec[v];
+            const RayRec* rv = rays + (size_t)v * n_bins;
+            const float* yv = y + (size_t)i * n_bins;
+            const bool hasx = vr.xlo <= vr.xhi, hasy = vr.ylo <= vr.yhi;
+            // The footprint is staged in chunks of kStageRays bins. The first
+            // chunk (in practice the only one) is handled outside any loop, so
+            // each class's projections are computed only when it is present.
+            auto chunk = [&](int base) {
+                const int top = min(j1, base + kStageRays - 1);
+                for (int q = lane; q <= top - base; q += 64) {
+                    const RayRec rr = rv[base + q];
+                    st[q] = make_float4(rr.pos_c, rr.dpos, yv[base + q] * rr.len, 0.f);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (hasx) bp_class<PX, true>(vr, st, base, max(vr.xlo, base), min(vr.xhi, top), cc, rc, c, r, mid_c,
+                                             mid_r, acc);
+                if (hasy) bp_class<PX, false>(vr, st, base, max(vr.ylo, base), min(vr.yhi, top), cc, rc, c, r, mid_c,
+                                              mid_r, acc);
+                // the slot is rewritten only after every lane's reads
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            };
+            chunk(j0);
+            for (int base = j0 + kStageRays; base <= j1; base += kStageRays) chunk(base);
+        }
+    }
+    if (VG > 1) {
+        if (wave > 0) {
+#pragma unroll
+            for (int a = 0; a < PX; ++a)
+#pragma unroll
+                for (int b = 0; b < PX; ++b) red[wave - 1][a * PX + b][lane] = acc[a][b];
+        }
+        __syncthreads();
+        if (wave > 0) return;
+        for (int w = 0; w < VG - 1; ++w)
+#pragma unroll
+            for (int a = 0; a < PX; ++a)
+#pragma unroll
+                for (int b = 0; b < PX; ++b) acc[a][b] += red[w][a * PX + b][lane];
+    }
+#pragma unroll
+    for (int dr = 0; dr < PX; ++dr)
+#pragma unroll
+        for (int dc = 0; dc < PX; ++dc) {
+            const int R = r + dr, C = c + dc;
+            if (R >= nys || C >= nxs) continue;
+            if (!kFused) {
+                xo[(size_t)R * nxs + C] = scale * acc[dr][dc];
+            } else {
+                // z = y_prev - (eta sigma / f^2) g on the f x f block of (R, C)
+                const float sg = scale * acc[dr][dc];
+                for (int a = 0; a < f; ++a) {
+                    const size_t row = (size_t)(f * R + a) * nx + (size_t)f * C;
+                    for (int bb = 0; bb < f; ++bb) z[row + bb] = yprev[row + bb] - sg;
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// TV-prox (Chambolle's dual projection), n_iter <= H-1 steps per launch with
+// the tile and a halo of H cells held in LDS. Cells within H of the tile edge
+// see incomplete neighbourhoods; the error travels one cell per step, so the
+// T x T output tile stays exact.
+// The dual field p is zero outside the image and stays zero on the last row
+// (p1) and last column (p2), because the masked gradient vanishes there; so
+// div p = p1[r] - p1[r-1] + p2[c] - p2[c-1] needs no boundary tests, and the
+// Neumann conditions live only in the two gradient masks.
+//   mode 0: x_out = z - lambda div p
+//   mode 1: x = (1-alpha) z + alpha (z - lambda div p); y_out = x + a_t (x - x_prev);
+//           x_out = x; hist (optional) = x
+//   p_in/p_out: optional global dual field [2][ny][nx] for multi-launch runs
+//   (p_out set: the launch stores p for its tile instead of producing x).
+// ---------------------------------------------------------------------------
+// Tile (bx, by) of the TV-prox, NT threads.
+template <int T, int H, int NT>
+__device__ __forceinline__ void tv_body(int bx, int by, const float* __restrict__ z, int nx, int ny, float lam,
+                                        float tau, int n_iter, const float* __restrict__ p_in,
+                                        float* __restrict__ p_out, int mode, float alpha, float a_t,
+                                        const float* __restrict__ x_prev, float* __restrict__ x_out,
+                                        float* __restrict__ y_out, float* __restrict__ hist, int pf, float pinv,
+                                        float* __restrict__ plx, int ppx, float* __restrict__ ply, int ppy,
+                                        int pnxs, int pnys) {
+    constexpr int S = T + 2 * H;
+    constexpr int NC = (S * S + NT - 1) / NT;
+    __shared__ float sz[S * S], sp1[S * S], sp2[S * S], su[S * S];
+    const int R0 = by * T - H, C0 = bx * T - H;
+    const size_t plane = (size_t)nx * ny;
+    // per-thread cells, their clamped neighbour indices and gradient masks
+    int ce[NC], cup[NC], cleft[NC], cdown[NC], cright[NC];
+    float m1[NC], m2[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int ee = e < S * S ? e : S * S - 1;
+        const int lr = ee / S, lc = ee - lr * S;
+        const int gr = R0 + lr, gc = C0 + lc;
+        const bool in = gr >= 0 && gr < ny && gc >= 0 && gc < nx;
+        ce[k] = e;
+        cup[k] = lr > 0 ? ee - S : ee;
+        cleft[k] = lc > 0 ? ee - 1 : ee;
+        cdown[k] = lr < S - 1 ? ee + S : ee;
+        cright[k] = lc < S - 1 ? ee + 1 : ee;
+        m1[k] = (in && gr < ny - 1) ? 1.f : 0.f;
+        m2[k] = (in && gc < nx - 1) ? 1.f : 0.f;
+        if (e < S * S) {
+            const size_t gi = (size_t)gr * nx + gc;
+            sz[e] = in ? z[gi] : 0.f;
+            sp1[e] = (in && p_in) ? p_in[gi] : 0.f;
+            sp2[e] = (in && p_in) ? p_in[plane + gi] : 0.f;
+        }
+    }
+    __syncthreads();
+    const float il = 1.f / lam;
+    for (int it = 0; it < n_iter; ++it) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int e = ce[k];
+            if (e < S * S) su[e] = (sp1[e] - sp1[cup[k]]) + (sp2[e] - sp2[cleft[k]]) - sz[e] * il;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int e = ce[k];
+            if (e < S * S) {
+                const float u = su[e];
+                const float q1 = m1[k] * (su[cdown[k]] - u);
+                const float q2 = m2[k] * (su[cright[k]] - u);
+                const float inv = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(fmaf(q1, q1, q2 * q2)), 1.f));
+                sp1[e] = fmaf(tau, q1, sp1[e]) * inv;
+                sp2[e] = fmaf(tau, q2, sp2[e]) * inv;
+            }
+        }
+        __syncthreads();
+    }
+    float* const yst = su;  // free after the last step: holds y_t for the pooling epilogue
+    for (int e = threadIdx.x; e < T * T; e += NT) {
+        const int tr = e / T, tc = e - tr * T;
+        const int gr = R0 + H + tr, gc = C0 + H + tc;
+        if (gr >= ny || gc >= nx) continue;
+        const int l = (H + tr) * S + (H + tc);
+        const size_t gi = (size_t)gr * nx + gc;
+        if (p_out) {
+            p_out[gi] = sp1[l];
+            p_out[plane + gi] = sp2[l];
+            continue;
+        }
+        const float d = (sp1[l] - sp1[l - S]) + (sp2[l] - sp2[l - 1]);
+        const float zz = sz[l];
+        const float den = fmaf(-lam, d, zz);
+        if (mode == 0) {
+            x_out[gi] = den;
+        } else {
+            const float xr = (1.f - alpha) * zz + alpha * den;
+            const float yn = fmaf(a_t, xr - x_prev[gi], xr);
+            x_out[gi] = xr;
+            y_out[gi] = yn;
+            if (hist) hist[gi] = xr;
+            yst[l] = yn;
+        }
+    }
+    if (pf > 0) {
+        // pooling of y_t for the next iteration's stage (pf x pf blocks inside
+        // this tile), written into that stage's two line images with the same
+        // arithmetic as k_prepare
+        __syncthreads();
+        const int tc = T / pf;
+        const int Rc0 = (R0 + H) / pf, Cc0 = (C0 + H) / pf;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int e = threadIdx.x; e < tc * tc; e += NT) {
+                // consecutive threads walk the contiguous axis of the image written
+                const int u = e % tc, w = e / tc;
+                const int cr = pass == 0 ? u : w, cc = pass == 0 ? w : u;
+                const int R = Rc0 + cr, C = Cc0 + cc;
+                if (R >= pnys || C >= pnxs) continue;
+                float sum = 0.f;
+                if (pf == 1) {
+                    sum = yst[(H + cr) * S + H + cc];
+                } else {
+                    for (int a = 0; a < pf; ++a)
+                        for (int b = 0; b < pf; ++b) sum += yst[(H + cr * pf + a) * S + H + cc * pf + b];
+                    sum *= pinv;
+                }
+                if (pass == 0) plx[(size_t)C * ppx + kPad + R] = sum;
+                else ply[(size_t)R * ppy + kPad + C] = sum;
+            }
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace fbpnp

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -50,6 +51,11 @@ struct Stage {
 
 }  // namespace fbpnp
 
+struct fb_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct fb_plan {
     fb_geom g{};
     std::vector<fbpnp::Stage> stages;
@@ -61,6 +67,7 @@ struct fb_plan {
     float* zbuf = nullptr;     // [ny][nx]
     float* vec = nullptr;      // power iteration: 2 x [ny][nx] + reductions
     size_t vec_floats = 0;
+    std::vector<fb_launch_config> cfg;  // per stage; zero fields: defaults
 };
 
 namespace fbpnp {
@@ -122,8 +129,21 @@ struct PoolTarget {
     float* ly = nullptr;
     int px = 0, py = 0, nxs = 0, nys = 0;
 };
+// tile: TV tile width (16 or 32), 0 for the default
 fb_status launch_tv_single(const float* z, int nx, int ny, float lam, float tau, int n_iter, const float* p_in,
                            float* p_out, int mode, float alpha, float a_t, const float* x_prev, float* x_out,
-                           float* y_out, float* hist, hipStream_t s, const PoolTarget& pt = PoolTarget());
+                           float* y_out, float* hist, hipStream_t s, const PoolTarget& pt = PoolTarget(),
+                           int tile = 0);
+
+// Captures what body launches on a private stream into an instantiated graph.
+fb_status capture_graph(const std::function<fb_status(hipStream_t)>& body, fb_graph** out);
+
+// Launch configurations: defaults, validation, and a plan stage's effective one.
+int default_fp_seg(long waves1);
+int default_bp_px(long npx);
+int default_bp_vg(int px, long nblk, int n_sel);
+int default_tv_tile(long tiles32);
+fb_status check_config(const fb_launch_config& c);
+fb_launch_config plan_config(const fb_plan* p, int stage, int n_sel);
 
 }  // namespace fbpnp

@@ -25,6 +25,9 @@ EXPORTS = [
     "sketch_down", "sketch_up", "fb_tv_workspace_bytes", "tv_prox", "pnp_step", "fb_graph_create",
     "fb_graph_launch", "fb_graph_destroy", "fb_tv_vjp_workspace_bytes", "tv_prox_vjp",
     "fb_pnp_vjp_workspace_bytes", "pnp_step_vjp", "fb_power_lipschitz", "fb_plan_view_samples",
+    "fb_plan_set_config", "fb_plan_get_config", "fb_batch_create", "fb_batch_destroy", "fb_batch_layout",
+    "fb_batch_slice_plan", "fb_batch_set_config", "fb_batch_get_config", "pnp_step_batched",
+    "fb_batch_graph_create", "fb_autotune", "fb_batch_autotune",
 ]
 
 
@@ -61,6 +64,26 @@ class PnpArgs(ctypes.Structure):
     ]
 
 
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("fp_seg", ctypes.c_int32), ("bp_px", ctypes.c_int32), ("bp_vg", ctypes.c_int32),
+                ("tv_tile", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchArgs(ctypes.Structure):
+    _fields_ = [
+        ("stage", ctypes.c_int32), ("n_sub", ctypes.c_int32), ("subset", ctypes.c_int32),
+        ("sigma", ctypes.c_float), ("alpha", ctypes.c_float), ("a_t", ctypes.c_float),
+        ("lambda_", ctypes.c_float), ("tau", ctypes.c_float), ("tv_iters", ctypes.c_int32),
+        ("eta", ctypes.c_void_p), ("b", ctypes.c_void_p), ("y_prev", ctypes.c_void_p), ("x_prev", ctypes.c_void_p),
+        ("x_out", ctypes.c_void_p), ("y_out", ctypes.c_void_p), ("history", ctypes.c_void_p),
+        ("next_stage", ctypes.c_int32), ("prepared", ctypes.c_int32),
+        ("events", ctypes.POINTER(ctypes.c_void_p)),
+    ]
+
+
 _lib = None
 
 
@@ -91,6 +114,18 @@ def load() -> ctypes.CDLL:
     lib.fb_graph_launch.argtypes = [vp, vp]
     lib.fb_graph_destroy.argtypes = [vp]
     lib.fb_plan_view_samples.argtypes = [vp, c_int, P(ctypes.c_int64)]
+    lib.fb_plan_set_config.argtypes = [vp, c_int, P(LaunchConfig)]
+    lib.fb_plan_get_config.argtypes = [vp, c_int, c_int, P(LaunchConfig)]
+    lib.fb_batch_create.argtypes = [P(Geom), c_int, c_int, P(ctypes.c_int32), P(vp)]
+    lib.fb_batch_destroy.argtypes = [vp]
+    lib.fb_batch_layout.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64)]
+    lib.fb_batch_slice_plan.argtypes = [vp, c_int, P(vp)]
+    lib.fb_batch_set_config.argtypes = [vp, c_int, P(LaunchConfig)]
+    lib.fb_batch_get_config.argtypes = [vp, c_int, c_int, P(LaunchConfig)]
+    lib.pnp_step_batched.argtypes = [vp, P(BatchArgs), vp]
+    lib.fb_batch_graph_create.argtypes = [vp, P(BatchArgs), c_int, P(vp)]
+    lib.fb_autotune.argtypes = [vp, c_int, ctypes.c_char_p, vp]
+    lib.fb_batch_autotune.argtypes = [vp, c_int, ctypes.c_char_p, vp]
     lib.fb_power_lipschitz.argtypes = [vp, c_int, c_int, P(ctypes.c_double), vp]
     lib.fb_tv_vjp_workspace_bytes.argtypes = [c_int, c_int, c_int]
     lib.fb_tv_vjp_workspace_bytes.restype = ctypes.c_size_t
@@ -153,10 +188,13 @@ class Geometry:
 class Plan:
     """Projector plan (fb_plan_create): one geometry, one stage per pooling factor."""
 
-    def __init__(self, geom: Geometry, factors=(1,)):
+    def __init__(self, geom: Geometry, factors=(1,), _borrowed=None):
         lib = load()
         self.geom = geom
         self.factors = [int(f) for f in factors]
+        self._owner = _borrowed  # a plan held by a batch is not destroyed here
+        if _borrowed is not None:
+            return
         arr = (ctypes.c_int32 * len(self.factors))(*self.factors)
         h = ctypes.c_void_p()
         _check(lib.fb_plan_create(ctypes.byref(geom.c()), len(self.factors), arr, ctypes.byref(h)))
@@ -168,8 +206,23 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None):
-            load().fb_plan_destroy(self._h)
+            if self._owner is None:
+                load().fb_plan_destroy(self._h)
             self._h = None
+
+    def set_config(self, stage: int, cfg: dict | None = None) -> None:
+        """Launch configuration of a stage (fb_launch_config fields; None or 0: defaults)."""
+        c = None if cfg is None else ctypes.byref(LaunchConfig(**cfg))
+        _check(load().fb_plan_set_config(self._h, stage, c))
+
+    def get_config(self, stage: int, n_sel: int | None = None) -> dict:
+        out = LaunchConfig()
+        _check(load().fb_plan_get_config(self._h, stage, n_sel or self.geom.n_views, ctypes.byref(out)))
+        return out.as_dict()
+
+    def autotune(self, n_sel: int | None = None, cache_path: str | None = None, stream=None) -> None:
+        cp = None if cache_path is None else os.fsencode(cache_path)
+        _check(load().fb_autotune(self._h, n_sel or self.geom.n_views, cp, _stream(stream)))
 
     def __del__(self):
         try:
@@ -263,15 +316,7 @@ def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float
     if events is not None:
         if len(events) != 6:
             raise ValueError("events: need six entries (fp, bp, TV; begin and end)")
-        handles = []
-        for ev in events:
-            if ev is None:
-                handles.append(None)
-                continue
-            if not ev.cuda_event:  # torch creates the event on its first record
-                ev.record()
-            handles.append(ev.cuda_event)
-        a.events = (ctypes.c_void_p * 6)(*handles)  # the struct keeps the array alive
+        a.events = _events(events)  # the struct keeps the array alive
     return a
 
 
@@ -313,6 +358,121 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many slices advanced together (fb_batch_create): geometries may differ, the
+    stage factors are shared. Images and sinograms live in packed arenas whose
+    offsets (floats) are image_offsets / sino_offsets."""
+
+    def __init__(self, geoms, factors=(1,)):
+        lib = load()
+        self.geoms = list(geoms)
+        self.factors = [int(f) for f in factors]
+        n = len(self.geoms)
+        garr = (Geom * n)(*[g.c() for g in self.geoms])
+        farr = (ctypes.c_int32 * len(self.factors))(*self.factors)
+        h = ctypes.c_void_p()
+        _check(lib.fb_batch_create(garr, n, len(self.factors), farr, ctypes.byref(h)))
+        self._h = h
+        io, so = (ctypes.c_int64 * (n + 1))(), (ctypes.c_int64 * (n + 1))()
+        _check(lib.fb_batch_layout(h, io, so))
+        self.image_offsets, self.sino_offsets = list(io), list(so)
+        self.image_size, self.sino_size = self.image_offsets[-1], self.sino_offsets[-1]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __len__(self):
+        return len(self.geoms)
+
+    def slice_plan(self, i: int) -> Plan:
+        """The batch's own plan of slice i (shares its workspace; not for concurrent use)."""
+        h = ctypes.c_void_p()
+        _check(load().fb_batch_slice_plan(self._h, i, ctypes.byref(h)))
+        p = Plan(self.geoms[i], self.factors, _borrowed=self)
+        p._h = h
+        return p
+
+    def image(self, arena: torch.Tensor, i: int) -> torch.Tensor:
+        g = self.geoms[i]
+        o = self.image_offsets[i]
+        return arena[o:o + g.nx * g.ny].view(g.ny, g.nx)
+
+    def sinogram(self, arena: torch.Tensor, i: int) -> torch.Tensor:
+        g = self.geoms[i]
+        o = self.sino_offsets[i]
+        return arena[o:o + g.n_views * g.n_bins].view(g.n_views, g.n_bins)
+
+    def set_config(self, stage: int, cfg: dict | None = None) -> None:
+        c = None if cfg is None else ctypes.byref(LaunchConfig(**cfg))
+        _check(load().fb_batch_set_config(self._h, stage, c))
+
+    def get_config(self, stage: int, n_sub: int = 1) -> dict:
+        out = LaunchConfig()
+        _check(load().fb_batch_get_config(self._h, stage, n_sub, ctypes.byref(out)))
+        return out.as_dict()
+
+    def autotune(self, n_sub: int = 1, cache_path: str | None = None, stream=None) -> None:
+        cp = None if cache_path is None else os.fsencode(cache_path)
+        _check(load().fb_batch_autotune(self._h, n_sub, cp, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().fb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _events(events):
+    handles = []
+    for ev in events:
+        if ev is None:
+            handles.append(None)
+            continue
+        if not ev.cuda_event:  # torch creates the event on its first record
+            ev.record()
+        handles.append(ev.cuda_event)
+    return (ctypes.c_void_p * 6)(*handles)
+
+
+def batch_args(batch: Batch, stage: int, b, y_prev, x_prev, x_out, y_out, eta: torch.Tensor, a_t: float,
+               n_sub: int = 1, subset: int = 0, sigma: float = 1.0, alpha: float = 1.0, lam: float = 0.01,
+               tau: float = 0.125, tv_iters: int = 5, history: torch.Tensor | None = None, events=None) -> BatchArgs:
+    """Arguments of one pnp_step_batched on arenas (b: sino_size floats, images:
+    image_size floats, eta: one step size per slice)."""
+    ni, ns = batch.image_size, batch.sino_size
+    a = BatchArgs(stage, n_sub, subset, sigma, alpha, a_t, lam, tau, tv_iters,
+                  _ptr(eta, numel=len(batch), name="eta"), _ptr(b, numel=ns, name="b"),
+                  _ptr(y_prev, numel=ni, name="y_prev"), _ptr(x_prev, numel=ni, name="x_prev"),
+                  _ptr(x_out, numel=ni, name="x_out"), _ptr(y_out, numel=ni, name="y_out"),
+                  _ptr(history, numel=ni, name="history"), -1, 0)
+    if events is not None:
+        if len(events) != 6:
+            raise ValueError("events: need six entries (fp, bp, TV; begin and end)")
+        a.events = _events(events)
+    return a
+
+
+def pnp_step_batched(batch: Batch, args: BatchArgs, stream=None) -> None:
+    _check(load().pnp_step_batched(batch.handle, ctypes.byref(args), _stream(stream)))
+
+
+class BatchGraph(Graph):
+    """A schedule of batched steps captured into one HIP graph (fb_batch_graph_create)."""
+
+    def __init__(self, batch: Batch, steps):
+        arr = (BatchArgs * len(steps))(*steps)
+        h = ctypes.c_void_p()
+        _check(load().fb_batch_graph_create(batch.handle, arr, len(steps), ctypes.byref(h)))
+        self._h = h
+        self._plan = batch
 
 
 def tv_prox_vjp(z: torch.Tensor, xbar: torch.Tensor, zbar: torch.Tensor, lam: float, n_iter: int = 5,

@@ -101,9 +101,11 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stddef.h>
 #include "fbpnp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fb_geom), offsetof(fb_geom, angle_step_rad),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fb_geom), offsetof(fb_geom, angle_step_rad),
          sizeof(fb_stage_info), sizeof(fb_pnp_args), offsetof(fb_pnp_args, b),
-         offsetof(fb_pnp_args, tv_iters), offsetof(fb_pnp_args, history));
+         offsetof(fb_pnp_args, tv_iters), offsetof(fb_pnp_args, history), offsetof(fb_pnp_args, events));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(fb_launch_config), sizeof(fb_batch_args), offsetof(fb_batch_args, eta),
+         offsetof(fb_batch_args, tv_iters), offsetof(fb_batch_args, history), offsetof(fb_batch_args, events));
   return 0;
 }
 """)
@@ -113,6 +115,8 @@ int main(void) {
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(fbpnp.Geom), fbpnp.Geom.angle_step_rad.offset, ctypes.sizeof(fbpnp.StageInfo),
             ctypes.sizeof(fbpnp.PnpArgs), fbpnp.PnpArgs.b.offset, fbpnp.PnpArgs.tv_iters.offset,
-            fbpnp.PnpArgs.history.offset]
+            fbpnp.PnpArgs.history.offset, fbpnp.PnpArgs.events.offset,
+            ctypes.sizeof(fbpnp.LaunchConfig), ctypes.sizeof(fbpnp.BatchArgs), fbpnp.BatchArgs.eta.offset,
+            fbpnp.BatchArgs.tv_iters.offset, fbpnp.BatchArgs.history.offset, fbpnp.BatchArgs.events.offset]
     assert got == want
     assert math.isclose(geom().c().angle_step_rad, 2 * math.pi / 90)
