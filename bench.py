@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the FP64 oracle timing")
     ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-PSNR comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice batched workload")
+    ap.add_argument("--batch-steps", type=int, default=3, help="timed replays of the batched schedule")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--profile", action="store_true",
                     help="short run for hardware-counter passes: two replays of the sketched schedule "
@@ -393,6 +395,11 @@ def main() -> int:
     if not args.no_ttp:
         ttp = time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x, y, xt, T)
 
+    # ---- the 64-slice batched form (its own workload; not part of the value above)
+    bat = None
+    if not args.no_batch:
+        bat = batched_section(torch, fbpnp, synth, args.batch_steps)
+
     # ---- FP64 oracle on host cores (bounded sample of the same schedule)
     cpu = None if args.no_cpu_baseline else cpu_baseline(synth, w, xt, sk_sched, eta, n_sub)
 
@@ -417,6 +424,7 @@ def main() -> int:
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "time_to_psnr": ttp,
+        "batched": bat,
     }
     print(json.dumps(result), flush=True)
     return 0
@@ -504,6 +512,131 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
     a, bb = out["sketched_ms2g"]["ms_to_p_star_minus_0.1"], out["full_pnp_fista"]["ms_to_p_star_minus_0.1"]
     out["speedup_to_p_star_minus_0.1"] = None if (a is None or bb is None) else round(bb / a, 3)
     log(f"time-to-PSNR: {out}")
+    return out
+
+
+def batched_section(torch, fbpnp, synth, steps):
+    """The batched form on its own workload: 64 independent slices of uneven sizes and
+    view counts, a two-stage sketched schedule (30 iterations at f = 2, 20 at f = 1, all
+    views, FISTA momentum), launch configurations from the autotuner, the 50 iterations
+    captured as one graph. Compared with the same slices reconstructed one after another
+    through per-slice graphs of pnp_step (default configurations)."""
+    bw = synth.BATCH_WORKLOADS["batch64"]
+    shapes = bw.shapes()
+    factors = [f for f, _ in bw.stages]
+    t0 = time.time()
+    gds = [synth.fan_geometry(n, V) for n, V in shapes]
+    batch = fbpnp.Batch([fbpnp.Geometry(**g) for g in gds], factors)
+    n = len(gds)
+    s_full = factors.index(1)
+    b_arena = torch.zeros(batch.sino_size, device="cuda")
+    eta = np.zeros((len(factors), n), dtype=np.float32)
+    samples = {f: 0 for f in factors}
+    for i, g in enumerate(gds):
+        sw = bw.slice_workload(i)
+        plan = batch.slice_plan(i)
+        xt = torch.from_numpy(synth.phantom(sw, i)).cuda().reshape(-1)
+        ax = torch.empty(g["n_views"] * g["n_bins"], device="cuda")
+        fbpnp.fanbeam_fp(plan, s_full, xt, ax)
+        eps = synth.standard_normal(synth.noise_seed(sw, i), (g["n_views"], g["n_bins"]))
+        bi = synth.add_noise(ax.cpu().numpy().astype(np.float64).reshape(eps.shape), eps, sw.noise_kind,
+                             sw.noise_level).astype(np.float32)
+        batch.sinogram(b_arena, i).copy_(torch.from_numpy(bi))
+        for k, f in enumerate(factors):
+            eta[k, i] = 1.0 / fbpnp.power_lipschitz(plan, k, 50)
+            samples[f] += plan.stage_info(k).samples_all_views
+    t_setup = time.time() - t0
+    t0 = time.time()
+    batch.autotune(1)
+    t_tune = time.time() - t0
+    cfgs = {f"f{f}": batch.get_config(k, 1) for k, f in enumerate(factors)}
+    log(f"batch: setup {t_setup:.1f}s, autotune {t_tune:.1f}s, configs {cfgs}")
+    eta_d = [torch.from_numpy(eta[k]).cuda() for k in range(len(factors))]
+    T = sum(it for _, it in bw.stages)
+    a = synth.momentum_table(T, bw.momentum)
+    stage_t = [k for k, (_, it) in enumerate(bw.stages) for _ in range(it)]
+    x = torch.zeros(batch.image_size, device="cuda")
+    y = torch.zeros(batch.image_size, device="cuda")
+
+    def args_for(events=None):
+        return [fbpnp.batch_args(batch, stage_t[t], b_arena, y, x, x, y, eta_d[stage_t[t]], float(a[t]),
+                                 alpha=bw.alpha, lam=bw.lam, tau=bw.tau, tv_iters=bw.tv_iters,
+                                 events=None if events is None else events[t]) for t in range(T)]
+
+    graph = fbpnp.BatchGraph(batch, args_for())
+
+    def run(g):
+        x.zero_()
+        y.zero_()
+        g.launch()
+
+    run(graph)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run(graph)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # per-kernel durations (direct calls, start/stop events per kernel)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(T)]
+    direct = args_for(evs)
+    fbpnp.chain_steps(direct)
+    x.zero_()
+    y.zero_()
+    for st in direct:
+        fbpnp.pnp_step_batched(batch, st)
+    torch.cuda.synchronize()
+    kern = {}
+    for t in range(T):
+        f = factors[stage_t[t]]
+        for k, name in ((0, "fp"), (2, "bp"), (4, "tv")):
+            kern.setdefault(f"{name}_f{f}", []).append(evs[t][k].elapsed_time(evs[t][k + 1]))
+    kernels = {}
+    for key, v in kern.items():
+        avg_ms = float(np.mean(v))
+        d = {"avg_launch_us": round(avg_ms * 1e3, 3), "launches_per_step": len(v)}
+        if not key.startswith("tv"):
+            smp = samples[int(key.split("_f")[1])]
+            d["gsamples_per_s"] = round(smp / (avg_ms * 1e-3) / 1e9, 2)
+        kernels[key] = d
+    # the same slices one after another (one graph per slice)
+    singles = []
+    for i, g in enumerate(gds):
+        plan = batch.slice_plan(i)
+        xi, yi = batch.image(x, i).reshape(-1), batch.image(y, i).reshape(-1)
+        bi = batch.sinogram(b_arena, i).reshape(-1)
+        st = [fbpnp.pnp_args(plan, stage_t[t], bi, yi, xi, xi, yi, float(eta[stage_t[t], i]), float(a[t]),
+                             alpha=bw.alpha, lam=bw.lam, tau=bw.tau, tv_iters=bw.tv_iters) for t in range(T)]
+        singles.append(fbpnp.Graph(plan, st))
+    for gi in singles:
+        gi.launch()
+    torch.cuda.synchronize()
+    e0.record()
+    for gi in singles:
+        gi.launch()
+    e1.record()
+    e1.synchronize()
+    ms_single = e0.elapsed_time(e1)
+    for gi in singles:
+        gi.close()
+    graph.close()
+    out = {
+        "workload": f"batch64: {n} slices, widths {sorted(set(s for s, _ in shapes))}, views "
+                    f"{sorted(set(v for _, v in shapes))}, bins 1.5 x width, stages f=2 x 30 then f=1 x 20, "
+                    "all views, TV-prox 5 x lambda 0.01, FISTA momentum",
+        "slice_iterations_per_s": round(n * T / (ms * 1e-3), 1),
+        "ms_per_batch_reconstruction": round(ms, 3),
+        "samples_per_full_res_projection": int(samples[1]),
+        "one_slice_at_a_time_ms": round(ms_single, 3),
+        "speedup_vs_one_slice_at_a_time": round(ms_single / ms, 3),
+        "configs": cfgs,
+        "kernels": kernels,
+        "autotune_s": round(t_tune, 2),
+    }
+    log(f"batch: {out}")
+    batch.close()
     return out
 
 

@@ -90,6 +90,48 @@ WORKLOADS = {
 }
 
 
+@dataclass
+class BatchWorkload:
+    """Many independent slices of uneven sizes and view counts, one shared stage schedule.
+    Slice i draws its width from `sizes` and its view count from `view_counts` (uniform,
+    seeded), has 1.5 n bins, and its phantom and noise seeds follow `slice_workload(i)`."""
+    name: str
+    n_slices: int
+    sizes: tuple
+    view_counts: tuple
+    n_ellipses: int
+    noise_kind: str
+    noise_level: float
+    stages: list
+    n_subsets: int
+    momentum: bool
+    lam: float = 0.01
+    tv_iters: int = 5
+    tau: float = 0.125
+    alpha: float = 1.0
+    seed_base: int = 0
+
+    def shapes(self) -> list:
+        """[(n, n_views)] per slice."""
+        rng = np.random.default_rng(4000 * self.seed_base)
+        n = rng.choice(np.asarray(self.sizes), self.n_slices)
+        v = rng.choice(np.asarray(self.view_counts), self.n_slices)
+        return [(int(a), int(b)) for a, b in zip(n, v)]
+
+    def slice_workload(self, i: int) -> Workload:
+        n, V = self.shapes()[i]
+        return Workload(f"{self.name}[{i}]", n, V, int(round(1.5 * n)), self.n_ellipses, False, self.noise_kind,
+                        self.noise_level, self.stages, self.n_subsets, self.momentum, self.lam, self.tv_iters,
+                        self.tau, self.alpha, self.seed_base)
+
+
+BATCH_WORKLOADS = {
+    # 64 slices, widths from {128, ..., 512}, 180 / 360 / 720 views, two-stage sketch (30 at f = 2, 20 at f = 1)
+    "batch64": BatchWorkload("batch64", 64, (128, 192, 256, 384, 512), (180, 360, 720), 20, "gaussian", 0.01,
+                             [(2, 30), (1, 20)], 0, True, seed_base=4),
+}
+
+
 def momentum_table(T: int, fista: bool = True) -> np.ndarray:
     """a_t for t = 1..T: (t-1)/(t+3) for the FISTA-type sequence of Sec. 3, else 0."""
     t = np.arange(1, T + 1, dtype=np.float64)
