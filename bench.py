@@ -312,6 +312,14 @@ def main() -> int:
 
     sk_sched = schedule(w.stages, 3000 * w.seed_base, n_sub)
     T = len(sk_sched)
+    # launch configurations for the subset size the iterations use (autotuner, HIP-event timed)
+    t0 = time.time()
+    import tempfile
+
+    tune_cache = os.path.join(tempfile.mkdtemp(prefix="fbpnp_tune_"), "launch_configs.txt")
+    plan.autotune(n_sel=V // n_sub, cache_path=tune_cache)
+    configs = {f"f{f}": plan.get_config(stage_of[f], V // n_sub) for f in factors}
+    log(f"autotune {time.time() - t0:.1f}s: {configs}")
     graph = fbpnp.Graph(plan, make_steps(sk_sched))
 
     def run_once(g):
@@ -393,7 +401,8 @@ def main() -> int:
     # ---- time-to-PSNR: sketched vs full-gradient PnP-FISTA vs full-resolution PnP-SGD
     ttp = None
     if not args.no_ttp:
-        ttp = time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x, y, xt, T)
+        ttp = time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x, y, xt, T, tune_cache)
+        plan.autotune(n_sel=V // n_sub, cache_path=tune_cache)  # back to the subset configuration
 
     # ---- the 64-slice batched form (its own workload; not part of the value above)
     bat = None
@@ -420,6 +429,7 @@ def main() -> int:
                                "1 of 8 view subsets, TV-prox 5 x lambda 0.01, FISTA momentum",
                    "iterations_per_step": T, "image": N, "views": V, "bins": B},
         "roofline": roofline,
+        "launch_configs": configs,
         "cpu_baseline": cpu,
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
@@ -430,7 +440,7 @@ def main() -> int:
     return 0
 
 
-def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x, y, xt, T):
+def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x, y, xt, T, tune_cache):
     """Per-iteration PSNR (from an iterate history) against cumulative GPU time, for the
     sketched schedule, full-gradient PnP-FISTA and full-resolution PnP-SGD."""
     N = w.n
@@ -439,6 +449,8 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
     peak = float(xt.max() - xt.min())
 
     def run(stages, n_sub_used, seed, t_offset=0, x_init=None):
+        # each method runs with the launch configurations tuned for its view count
+        plan.autotune(n_sel=w.n_views // n_sub_used if n_sub_used else w.n_views, cache_path=tune_cache)
         sched = schedule(stages, seed, n_sub_used, True, t_offset)
         hist = torch.empty((len(sched), npix), device="cuda")
         stage_blocks = []

@@ -99,8 +99,8 @@ fb_status fb_plan_view_samples(const fb_plan* plan, int stage, int64_t* out);
  * Launch configuration of a stage's kernels (no effect on what is computed,
  * only on how the work is split; results can differ in the last bits where
  * the split changes a summation order):
- *   fp_seg   lanes per ray in the forward projector (1, 2 or 4; a wavefront
- *            holds 64 / fp_seg rays, a work-group 256 / fp_seg)
+ *   fp_seg   lanes per ray in the forward projector (1, 2, 4 or 8; a
+ *            wavefront holds 64 / fp_seg rays, a work-group 256 / fp_seg)
  *   bp_px    pixels per lane side in the backprojector (1, 2 or 4; a
  *            wavefront owns an 8 bp_px square)
  *   bp_vg    wavefronts per work-group splitting the views (1..16, <= 4 when

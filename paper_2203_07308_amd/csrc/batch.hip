@@ -228,7 +228,8 @@ fb_status launch_fp_batch(fb_batch* B, int stage, int n_sub, int subset, const f
     const ItemTable* t;
     fb_status st = work_items(B, 1, stage, seg, n_sub, s, &t);
     if (st != FB_OK) return st;
-    if (seg == 4) FB_BLAUNCH(k_fp_batch<4>, dim3(t->n), dim3(256), s, B->d_desc, t->d, stage, subset, n_sub, b);
+    if (seg == 8) FB_BLAUNCH(k_fp_batch<8>, dim3(t->n), dim3(256), s, B->d_desc, t->d, stage, subset, n_sub, b);
+    else if (seg == 4) FB_BLAUNCH(k_fp_batch<4>, dim3(t->n), dim3(256), s, B->d_desc, t->d, stage, subset, n_sub, b);
     else if (seg == 2) FB_BLAUNCH(k_fp_batch<2>, dim3(t->n), dim3(256), s, B->d_desc, t->d, stage, subset, n_sub, b);
     else FB_BLAUNCH(k_fp_batch<1>, dim3(t->n), dim3(256), s, B->d_desc, t->d, stage, subset, n_sub, b);
     return check_launch("batched fp");

@@ -203,10 +203,11 @@ __device__ __forceinline__ void cand_range(float j1, float j2, int lo, int hi, i
 // every difference involved is representable; within one rounding otherwise).
 template <int PX>
 __device__ __forceinline__ void strip_add(float p, float qf, float yy, float (&s)[PX]) {
-    const float e = p - qf;
 #pragma unroll
     for (int t = 0; t < PX; ++t) {
-        const float wt = fmaxf(1.f - fabsf(e - (float)t), 0.f);
+        // 1 - |p - q| is at most 1, so clamping it to [0, 1] is the max with 0
+        // (one subtraction with the output clamp)
+        const float wt = __builtin_amdgcn_fmed3f(1.f - fabsf(p - (qf + (float)t)), 0.f, 1.f);
         s[t] = fmaf(wt, yy, s[t]);
     }
 }
@@ -218,8 +219,10 @@ template <int PX>
 __device__ __forceinline__ void gather_strip(const float4* __restrict__ st, int base, int jl, int jh, float kf,
                                              int qm, float (&s)[PX]) {
     const float qf = (float)qm;
-    for (int j = jl; j <= jh; ++j) {
-        const float4 e = st[j - base];
+    // walk the staged records by address (one counter for the loop and the load)
+    const float4* const end = st + (jh - base);
+    for (const float4* e4 = st + (jl - base); e4 <= end; ++e4) {
+        const float4 e = *e4;
         strip_add<PX>(fmaf(kf, e.y, e.x), qf, e.z, s);
     }
 }

@@ -213,7 +213,7 @@ fb_status check_config(const fb_launch_config& c) {
             if (v == o) return true;
         return false;
     };
-    if (!in(c.fp_seg, {1, 2, 4})) return fail(FB_EINVAL, "launch config: fp_seg must be 0, 1, 2 or 4");
+    if (!in(c.fp_seg, {1, 2, 4, 8})) return fail(FB_EINVAL, "launch config: fp_seg must be 0, 1, 2, 4 or 8");
     if (!in(c.bp_px, {1, 2, 4})) return fail(FB_EINVAL, "launch config: bp_px must be 0, 1, 2 or 4");
     if (!in(c.bp_vg, {1, 2, 4, 8, 16})) return fail(FB_EINVAL, "launch config: bp_vg must be 0, 1, 2, 4, 8 or 16");
     if (c.bp_px == 4 && c.bp_vg > 4) return fail(FB_EINVAL, "launch config: bp_px = 4 allows bp_vg <= 4");
@@ -248,11 +248,13 @@ fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* view
     FB_LAUNCH((k_fp<RES, SG>), dim3(blocks), dim3(256), s, st.rays, nb, bp, views, n_sel, p->g.n_views, L.lx,   \
               L.ly_off, L.bytes, st.pitch_x, st.pitch_y, st.nxs, st.nys, b, y)
     if (resid) {
-        if (seg == 4) FB_FP(true, 4);
+        if (seg == 8) FB_FP(true, 8);
+        else if (seg == 4) FB_FP(true, 4);
         else if (seg == 2) FB_FP(true, 2);
         else FB_FP(true, 1);
     } else {
-        if (seg == 4) FB_FP(false, 4);
+        if (seg == 8) FB_FP(false, 8);
+        else if (seg == 4) FB_FP(false, 4);
         else if (seg == 2) FB_FP(false, 2);
         else FB_FP(false, 1);
     }

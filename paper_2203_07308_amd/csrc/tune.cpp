@@ -201,11 +201,13 @@ static fb_status autotune_plan(fb_plan* p, int n_sel, const char* cache_path, hi
     // n_sel views spread evenly over the scan, as an interleaved subset is
     std::vector<int32_t> hv(n_sel);
     for (int i = 0; i < n_sel; ++i) hv[i] = (int32_t)(((long)i * V) / n_sel);
-    DevBuf views, img, sino, b, out, yprev, xprev;
+    // proj: a projection of the selected views [n_sel][nb]; out: an image [ny][nx]
+    const size_t nproj = (size_t)n_sel * nb;
+    DevBuf views, img, sino, b, proj, out, yprev, xprev;
     if ((st = views.alloc(n_sel * sizeof(int32_t))) != FB_OK || (st = img.alloc(npix * 4)) != FB_OK ||
-        (st = sino.alloc((size_t)n_sel * nb * 4)) != FB_OK || (st = b.alloc((size_t)V * nb * 4)) != FB_OK ||
-        (st = out.alloc(npix * 4)) != FB_OK || (st = yprev.alloc(npix * 4)) != FB_OK ||
-        (st = xprev.alloc(npix * 4)) != FB_OK)
+        (st = sino.alloc(nproj * 4)) != FB_OK || (st = b.alloc((size_t)V * nb * 4)) != FB_OK ||
+        (st = proj.alloc(nproj * 4)) != FB_OK || (st = out.alloc(npix * 4)) != FB_OK ||
+        (st = yprev.alloc(npix * 4)) != FB_OK || (st = xprev.alloc(npix * 4)) != FB_OK)
         return st;
     if (hipMemcpy(views.p, hv.data(), hv.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
         return fail(FB_EHIP, "autotune: upload");
@@ -233,16 +235,16 @@ static fb_status autotune_plan(fb_plan* p, int n_sel, const char* cache_path, hi
         if ((st = launch_prepare(p, k, img.f(), nx, S.f, s)) != FB_OK) return st;
         // forward projection (residual form, as in the iteration)
         std::vector<int> segs = {def.fp_seg};
-        for (int v : {1, 2, 4})
+        for (int v : {1, 2, 4, 8})
             if (v != def.fp_seg) segs.push_back(v);
         int seg = def.fp_seg;
         st = pick<int>(
             segs,
             [&](const int& c) {
                 p->cfg[k].fp_seg = c;
-                return launch_fp(p, k, true, vp, n_sel, b.f(), out.f(), s);
+                return launch_fp(p, k, true, vp, n_sel, b.f(), proj.f(), s);
             },
-            [&](std::vector<float>& h) { return download(h, out.f(), (size_t)n_sel * nb); }, s, &seg);
+            [&](std::vector<float>& h) { return download(h, proj.f(), nproj); }, s, &seg);
         if (st != FB_OK) return st;
         p->cfg[k].fp_seg = seg;
         // backprojection: the fused form is timed, the plain gradient compared
@@ -329,7 +331,7 @@ static fb_status autotune_batch(fb_batch* B, int n_sub, const char* cache_path, 
         const fb_launch_config def = batch_config(B, k, n_sub);
         if ((st = launch_prepare_batch(B, k, img.f(), s)) != FB_OK) return st;
         std::vector<int> segs = {def.fp_seg};
-        for (int v : {1, 2, 4})
+        for (int v : {1, 2, 4, 8})
             if (v != def.fp_seg) segs.push_back(v);
         int seg = def.fp_seg;
         st = pick<int>(

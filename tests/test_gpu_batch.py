@@ -172,7 +172,7 @@ def test_batched_slice_matches_oracle_loop():
 
 def candidate_configs():
     out = []
-    for seg in (1, 2, 4):
+    for seg in (1, 2, 4, 8):
         for px, vg in ((1, 1), (1, 4), (2, 2), (2, 16), (4, 1), (4, 4)):
             for tile in (16, 32):
                 out.append(dict(fp_seg=seg, bp_px=px, bp_vg=vg, tv_tile=tile))
@@ -201,7 +201,7 @@ def test_batched_autotuner_candidates_agree_and_cache(tmp_path):
     lines = cache.read_text().splitlines()
     assert len(lines) == len(FACTORS)
     for c in tuned:
-        assert c["fp_seg"] in (1, 2, 4) and c["bp_px"] in (1, 2, 4) and c["tv_tile"] in (16, 32)
+        assert c["fp_seg"] in (1, 2, 4, 8) and c["bp_px"] in (1, 2, 4) and c["tv_tile"] in (16, 32)
     got = host(run_batched(batch, b_arena, sched, eta))
     assert rel(got, base) <= 1e-5
     # a second batch of the same slices takes the cached choice (no new cache lines)
@@ -236,7 +236,24 @@ def test_plan_configs_match_oracle_and_autotune(tmp_path):
     plan.autotune(len(views), str(tmp_path / "t.txt"))
     for k in range(2):
         c = plan.get_config(k, len(views))
-        assert c["fp_seg"] in (1, 2, 4) and c["bp_vg"] >= 1
+        assert c["fp_seg"] in (1, 2, 4, 8) and c["bp_vg"] >= 1
+
+
+def test_plan_autotune_all_views_sinogram_larger_than_image(tmp_path):
+    """Autotuning with every view selected, where a projection (90 x 96) holds more
+    values than the image (64 x 64): the tuner's projection buffer is sized for it."""
+    g = synth.fan_geometry(64, 90)
+    og = oracle.Geometry(**g)
+    plan = fbpnp.Plan(fbpnp.Geometry(**g), [2, 1])
+    say("plan autotune all views")
+    plan.autotune(90, str(tmp_path / "t.txt"))
+    img = synth.rasterise(synth.random_ellipses(6, 8, 64), 64)
+    for k, f in enumerate((2, 1)):
+        v = oracle.down(img, f)
+        y = torch.empty(90 * g["n_bins"], device="cuda")
+        fbpnp.fanbeam_fp(plan, k, dev(v).reshape(-1), y)
+        ref = oracle.fp(og, v, f=f)
+        assert rel(host(y).reshape(ref.shape), ref) <= 1e-5, (k, plan.get_config(k, 90))
 
 
 def test_batch_rejects_bad_arguments():
