@@ -39,9 +39,24 @@ FLOP_PER_TV_PIXEL_ITER = 20
 FLOP_PER_TV_PIXEL_OUT = 8
 KERNEL_DESCRIPTION = {"fp": "Joseph forward projection minus b", "bp": "matched gather back-projection fused with the "
                       "gradient step", "tv": "TV-prox with relaxation, momentum and pooling epilogue"}
-KERNEL_SOURCES = ["paper_2203_07308_amd/csrc/kernels.hip", "paper_2203_07308_amd/csrc/fbpnp_impl.h",
-                  "paper_2203_07308_amd/csrc/plan.cpp"]
+KERNEL_SOURCES = ["paper_2203_07308_amd/csrc/" + f for f in
+                  ("device.h", "kernels.hip", "fbpnp_impl.h", "plan.cpp", "tune.cpp")]
 TRAFFIC_SUMMARY = "profiles/ms2g512_hbm_traffic.md"
+SHIPPED_TUNE_CACHE = "paper_2203_07308_amd/tuned/mi355x_launch_configs.txt"
+
+
+def tune_cache_path(args) -> str:
+    """The autotuner cache file this run uses (see --tune-cache / --retune)."""
+    import shutil
+    import tempfile
+
+    if args.tune_cache:
+        return args.tune_cache
+    path = os.path.join(tempfile.mkdtemp(prefix="fbpnp_tune_"), "launch_configs.txt")
+    shipped = os.path.join(ROOT, SHIPPED_TUNE_CACHE)
+    if not args.retune and os.path.exists(shipped):
+        shutil.copyfile(shipped, path)
+    return path
 
 
 def kernel_source_hash() -> str:
@@ -85,6 +100,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the FP64 oracle timing")
     ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-PSNR comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice batched workload")
+    ap.add_argument("--tune-cache", metavar="PATH",
+                    help="autotuner cache to read and extend (default: a temporary copy of the shipped "
+                         "MI355X cache, so a run never edits the tree)")
+    ap.add_argument("--retune", action="store_true", help="start from an empty autotuner cache")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="run the autotuner for every launch the bench makes (with --tune-cache), then exit")
     ap.add_argument("--batch-steps", type=int, default=3, help="timed replays of the batched schedule")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--profile", action="store_true",
@@ -96,6 +117,10 @@ def parse():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the HBM traffic summary of two rocprofv3 --pmc runs of --profile "
                          "(FETCH_SIZE, then WRITE_SIZE), calibrated by the 64 MiB copy (no GPU use)")
+    ap.add_argument("--counters", nargs="*", default=[], metavar="DIR",
+                    help="with --pmc-summary: further rocprofv3 --pmc output directories (any counters), averaged "
+                         "per iteration group; with --trace-dir, VALU utilisation and L2 hit rate are derived")
+    ap.add_argument("--trace-dir", help="with --pmc-summary: a kernel-trace directory for per-group durations")
     ap.add_argument("--cmd", default="", help="command line quoted in a summary")
     ap.add_argument("--bench-log", help="log of the profiled command (its JSON line is quoted in a trace summary)")
     return ap.parse_args()
@@ -137,31 +162,33 @@ def _csv(directory: str, suffix: str):
 
 def label_dispatches(names):
     """(group, index) labels of the dispatches that belong to complete replays of the
-    sketched schedule, e.g. ("bp_f1", i): a replay starts at the pooling kernel followed by
-    the first residual projection and has one denoiser launch per iteration."""
+    sketched schedule, e.g. ("bp_f1", i): a replay is the pooling kernel followed by
+    exactly one forward projection, back-projection and denoiser launch per iteration
+    (other sequences, such as the autotuner's timing runs, are skipped)."""
     from paper_2203_07308_amd import synth
 
     w = synth.WORKLOADS["ms2g512"]
     stage_f = [f for f, n in w.stages for _ in range(n)]
     T = len(stage_f)
-    cls = {"k_fp": "fp", "k_bp": "bp", "k_tv": "tv", "k_prepare": "prepare"}
+    want = ("k_fp<true", "k_bp<", "k_tv<")
     out = []
     i = 0
-    while i + 1 < len(names):
-        if not (names[i] == "k_prepare" and names[i + 1].startswith("k_fp<true")):
+    while i < len(names):
+        if names[i] != "k_prepare":
             i += 1
             continue
-        lab, t, j = [], 0, i
-        while j < len(names) and t < T:
-            c = next((v for k, v in cls.items() if names[j].startswith(k)), None)
-            if c is None:
+        lab, j = [("prepare_f%d" % stage_f[0], i)], i + 1
+        for t in range(T):
+            if j + 3 > len(names) or not all(names[j + k].startswith(want[k]) for k in range(3)):
                 break
-            lab.append((f"{c}_f{stage_f[t]}", j))
-            t += c == "tv"
-            j += 1
-        if t == T:
+            for k, c in enumerate(("fp", "bp", "tv")):
+                lab.append((f"{c}_f{stage_f[t]}", j + k))
+            j += 3
+        else:
             out += lab
-        i = j
+            i = j
+            continue
+        i += 1
     return out
 
 
@@ -239,8 +266,52 @@ def pmc_summary(args) -> int:
         kn = sorted(set(n for n, _ in groups[g]))
         out.append(f"| {g} | {', '.join('`' + k + '`' for k in kn)} | {len(fv)} | {fk:.1f} | {wk:.1f} | "
                    f"{rb:.0f} | {wb:.0f} | {rb + wb:.0f} |")
+    if args.counters:
+        out += counter_tables(args)
     print("\n".join(out))
     return 0
+
+
+# MI355X: 256 CUs x 4 SIMDs; a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
+N_SIMD, VALU_CYCLES, CLOCK_GHZ = 1024, 4, 2.4
+
+
+def counter_tables(args):
+    """Per-group averages of further counter passes, and derived figures: VALU busy
+    fraction = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x cycles of the kernel's duration),
+    L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS)."""
+    per = {}
+    for d in args.counters:
+        rows = _csv(d, "counter_collection.csv")
+        by_counter = {}
+        for r in rows:
+            by_counter.setdefault(r["Counter_Name"], []).append(r)
+        for cname, rs in by_counter.items():
+            rs.sort(key=lambda r: int(r["Dispatch_Id"]))
+            names = [_short(r["Kernel_Name"]) for r in rs]
+            for g, j in label_dispatches(names):
+                per.setdefault(g, {}).setdefault(cname, []).append(float(rs[j]["Counter_Value"]))
+    dur = {}
+    if args.trace_dir:
+        trace = _csv(args.trace_dir, "kernel_trace.csv")
+        trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+        names = [_short(r["Kernel_Name"]) for r in trace]
+        for g, j in label_dispatches(names):
+            dur.setdefault(g, []).append((int(trace[j]["End_Timestamp"]) - int(trace[j]["Start_Timestamp"])) * 1e-3)
+    cnames = sorted({c for v in per.values() for c in v})
+    out = ["", "## Further counters (average per dispatch)", "",
+           "| group | " + " | ".join(cnames) + " | avg us (trace) | VALU busy | L2 hit |",
+           "|---" * (len(cnames) + 4) + "|"]
+    for g in sorted(per, key=lambda k: (k.split("_f")[0], -int(k.split("_f")[1]))):
+        m = {c: sum(v) / len(v) for c, v in per[g].items()}
+        us = sum(dur[g]) / len(dur[g]) if g in dur else None
+        valu = (f"{m['SQ_INSTS_VALU'] * VALU_CYCLES / (N_SIMD * us * 1e-6 * CLOCK_GHZ * 1e9):.2f}"
+                if us and "SQ_INSTS_VALU" in m else "")
+        hit = (f"{m['TCC_HIT_sum'] / (m['TCC_HIT_sum'] + m['TCC_MISS_sum']):.3f}"
+               if "TCC_HIT_sum" in m and "TCC_MISS_sum" in m and m["TCC_HIT_sum"] + m["TCC_MISS_sum"] > 0 else "")
+        out.append(f"| {g} | " + " | ".join(f"{m[c]:.0f}" if c in m else "" for c in cnames) +
+                   f" | {'' if us is None else f'{us:.2f}'} | {valu} | {hit} |")
+    return out
 
 
 def main() -> int:
@@ -314,9 +385,13 @@ def main() -> int:
     T = len(sk_sched)
     # launch configurations for the subset size the iterations use (autotuner, HIP-event timed)
     t0 = time.time()
-    import tempfile
-
-    tune_cache = os.path.join(tempfile.mkdtemp(prefix="fbpnp_tune_"), "launch_configs.txt")
+    tune_cache = tune_cache_path(args)
+    if args.tune_only:
+        for n_sel in (V, V // n_sub):
+            plan.autotune(n_sel=n_sel, cache_path=tune_cache)
+        batched_section(torch, fbpnp, synth, 0, tune_cache, tune_only=True)
+        log(f"autotuner cache written to {tune_cache}")
+        return 0
     plan.autotune(n_sel=V // n_sub, cache_path=tune_cache)
     configs = {f"f{f}": plan.get_config(stage_of[f], V // n_sub) for f in factors}
     log(f"autotune {time.time() - t0:.1f}s: {configs}")
@@ -407,7 +482,7 @@ def main() -> int:
     # ---- the 64-slice batched form (its own workload; not part of the value above)
     bat = None
     if not args.no_batch:
-        bat = batched_section(torch, fbpnp, synth, args.batch_steps)
+        bat = batched_section(torch, fbpnp, synth, args.batch_steps, tune_cache)
 
     # ---- FP64 oracle on host cores (bounded sample of the same schedule)
     cpu = None if args.no_cpu_baseline else cpu_baseline(synth, w, xt, sk_sched, eta, n_sub)
@@ -527,7 +602,7 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
     return out
 
 
-def batched_section(torch, fbpnp, synth, steps):
+def batched_section(torch, fbpnp, synth, steps, tune_cache, tune_only=False):
     """The batched form on its own workload: 64 independent slices of uneven sizes and
     view counts, a two-stage sketched schedule (30 iterations at f = 2, 20 at f = 1, all
     views, FISTA momentum), launch configurations from the autotuner, the 50 iterations
@@ -559,8 +634,11 @@ def batched_section(torch, fbpnp, synth, steps):
             samples[f] += plan.stage_info(k).samples_all_views
     t_setup = time.time() - t0
     t0 = time.time()
-    batch.autotune(1)
+    batch.autotune(1, tune_cache)
     t_tune = time.time() - t0
+    if tune_only:
+        batch.close()
+        return None
     cfgs = {f"f{f}": batch.get_config(k, 1) for k, f in enumerate(factors)}
     log(f"batch: setup {t_setup:.1f}s, autotune {t_tune:.1f}s, configs {cfgs}")
     eta_d = [torch.from_numpy(eta[k]).cuda() for k in range(len(factors))]

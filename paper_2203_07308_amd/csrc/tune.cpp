@@ -27,8 +27,9 @@ using namespace fbpnp;
 
 namespace {
 
-constexpr int kWarm = 2, kReps = 8;
+constexpr int kWarm = 2, kReps = 8, kRounds = 5;
 constexpr double kAgree = 1e-5;
+constexpr float kMargin = 0.03f;  // a candidate replaces the default only if >= 3 % faster
 
 struct DevBuf {
     void* p = nullptr;
@@ -98,21 +99,45 @@ fb_status time_ms(const std::function<fb_status()>& run, hipStream_t s, float* m
     return st;
 }
 
-// The fastest candidate whose output agrees with the first one's.
+// The fastest candidate whose output agrees with the first one's (the
+// default). Each candidate's time is the median of kRounds rounds, the rounds
+// interleaved over the candidates so that clock or thermal drift affects all
+// alike; another candidate replaces the default only when it is at least
+// kMargin faster.
 template <typename Cand>
 fb_status pick(const std::vector<Cand>& cands, const std::function<fb_status(const Cand&)>& run,
                const std::function<fb_status(std::vector<float>&)>& read, hipStream_t s, Cand* best) {
+    const size_t n = cands.size();
+    std::vector<char> ok(n, 1);
     std::vector<float> ref, out;
-    float best_ms = INFINITY;
-    for (size_t i = 0; i < cands.size(); ++i) {
-        float ms;
-        fb_status st = time_ms([&] { return run(cands[i]); }, s, &ms);
+    for (size_t i = 0; i < n; ++i) {  // agreement with the default
+        fb_status st = run(cands[i]);
         if (st != FB_OK) return st;
         if (hipStreamSynchronize(s) != hipSuccess) return fail(FB_EHIP, "autotune: sync");
         if ((st = read(i == 0 ? ref : out)) != FB_OK) return st;
-        if (i > 0 && !(rel_l2(out, ref) <= kAgree)) continue;  // disagreeing candidates are never chosen
-        if (ms < best_ms) {
-            best_ms = ms;
+        if (i > 0) ok[i] = rel_l2(out, ref) <= kAgree;  // disagreeing candidates are never chosen
+    }
+    std::vector<std::vector<float>> t(n);
+    for (int round = 0; round < kRounds; ++round)
+        for (size_t i = 0; i < n; ++i) {
+            if (!ok[i]) continue;
+            float ms;
+            fb_status st = time_ms([&] { return run(cands[i]); }, s, &ms);
+            if (st != FB_OK) return st;
+            t[i].push_back(ms);
+        }
+    auto median = [](std::vector<float> v) {
+        std::sort(v.begin(), v.end());
+        return v[v.size() / 2];
+    };
+    const float t0 = median(t[0]);
+    float best_ms = t0 * (1.f - kMargin);
+    *best = cands[0];
+    for (size_t i = 1; i < n; ++i) {
+        if (!ok[i]) continue;
+        const float m = median(t[i]);
+        if (m < best_ms) {
+            best_ms = m;
             *best = cands[i];
         }
     }

@@ -32,6 +32,9 @@ def test_label_dispatches_groups_every_replay():
     # a truncated replay is not counted
     lab2 = bench.label_dispatches(names[: 2 + 181 + 2 + 100])
     assert len(lab2) == 181
+    # a tuning run (pooling, then repeated projections) is not a replay
+    tuning = ["k_prepare"] + ["k_fp<true, 4>"] * 10 + ["k_bp<8, 2, true>"] * 10 + ["k_tv<32, 6, 1024>"] * 10
+    assert bench.label_dispatches(tuning + names) == [(g, j + len(tuning)) for g, j in lab]
 
 
 def test_launch_traffic_reads_matching_summary(tmp_path):
