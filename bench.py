@@ -100,6 +100,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the FP64 oracle timing")
     ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-PSNR comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice batched workload")
+    ap.add_argument("--no-scenarios", action="store_true",
+                    help="skip the paper's three scenarios (sparse-view, low-dose, limited-angle)")
     ap.add_argument("--tune-cache", metavar="PATH",
                     help="autotuner cache to read and extend (default: a temporary copy of the shipped "
                          "MI355X cache, so a run never edits the tree)")
@@ -484,6 +486,11 @@ def main() -> int:
     if not args.no_batch:
         bat = batched_section(torch, fbpnp, synth, args.batch_steps, tune_cache)
 
+    # ---- the paper's own experiment shapes: two-stage sketch against PnP-FISTA
+    scen = None
+    if not args.no_scenarios:
+        scen = paper_scenarios(torch, fbpnp, synth, tune_cache)
+
     # ---- FP64 oracle on host cores (bounded sample of the same schedule)
     cpu = None if args.no_cpu_baseline else cpu_baseline(synth, w, xt, sk_sched, eta, n_sub)
 
@@ -510,6 +517,7 @@ def main() -> int:
                     for k, v in kernels.items()},
         "time_to_psnr": ttp,
         "batched": bat,
+        "paper_scenarios": scen,
     }
     print(json.dumps(result), flush=True)
     return 0
@@ -727,6 +735,101 @@ def batched_section(torch, fbpnp, synth, steps, tune_cache, tune_only=False):
     }
     log(f"batch: {out}")
     batch.close()
+    return out
+
+
+def psnr_vs_time(torch, fbpnp, plan, stage_of, b, xt, blocks, eta, alpha, lam, tau, tv_iters, reps=5):
+    """Runs consecutive stage blocks [(f, iterations)] from x = y = 0 with FISTA momentum
+    (t global), one captured graph per block with an iterate history; returns per-iteration
+    PSNR against xt and cumulative GPU time (each block's graph replayed `reps` times, the
+    median per iteration; the work does not depend on the values)."""
+    from paper_2203_07308_amd import synth
+
+    ny, nx = xt.shape
+    npix = nx * ny
+    T = sum(n for _, n in blocks)
+    a = synth.momentum_table(T)
+    x = torch.zeros(npix, device="cuda")
+    y = torch.zeros(npix, device="cuda")
+    hist = torch.empty((T, npix), device="cuda")
+    graphs, t = [], 0
+    for f, n in blocks:
+        steps = [fbpnp.pnp_args(plan, stage_of[f], b, y, x, x, y, eta[f], float(a[t + i]), None, 1.0, alpha, lam, tau,
+                                tv_iters, hist[t + i]) for i in range(n)]
+        graphs.append((n, fbpnp.Graph(plan, steps)))
+        t += n
+    for _, g in graphs:
+        g.launch()
+    torch.cuda.synchronize()
+    ref = torch.from_numpy(xt).cuda().reshape(1, -1).double()
+    peak = float(xt.max() - xt.min())
+    psnr = (10 * torch.log10(peak ** 2 / ((hist.double() - ref) ** 2).mean(dim=1))).cpu().numpy()
+    per_iter = []
+    for n, g in graphs:
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.launch()
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        per_iter += [float(np.median(times)) / n] * n
+        g.close()
+    return psnr, np.cumsum(per_iter)
+
+
+def paper_scenarios(torch, fbpnp, synth, tune_cache):
+    """The paper's experiments (Sec. 3) on synthetic disk phantoms: sparse-view, low-dose
+    and limited-angle fan-beam CT at 256^2 with 228 bins and Poisson transmission data;
+    PnP-MS2G Option 1 with the two-stage sketch (25 iterations at f = 4, 75 at f = 2)
+    against PnP-FISTA (100 full-gradient iterations), same TV-prox denoiser, eta = 1/L per
+    stage, FISTA momentum. Reports each method's PSNR curve, and the GPU time and the
+    projector work (Joseph samples of forward and back-projection) each needs to come
+    within 0.1 / 0.5 / 1 dB of PnP-FISTA's final PSNR."""
+    out = {}
+    for name, sc in synth.SCENARIOS.items():
+        g = sc.geometry
+        V, B = g["n_views"], g["n_bins"]
+        factors = [4, 2, 1]
+        stage_of = {f: i for i, f in enumerate(factors)}
+        plan = fbpnp.Plan(fbpnp.Geometry(**g), factors)
+        plan.autotune(n_sel=V, cache_path=tune_cache)
+        xt = sc.phantom()
+        ax = torch.empty(V * B, device="cuda")
+        fbpnp.fanbeam_fp(plan, stage_of[1], torch.from_numpy(xt).cuda().reshape(-1), ax)
+        b_np = sc.data(ax.cpu().numpy().astype(np.float64).reshape(V, B)).astype(np.float32)
+        b = torch.from_numpy(b_np).cuda().reshape(-1)
+        eta = {f: 1.0 / fbpnp.power_lipschitz(plan, stage_of[f], 100) for f in factors}
+        kw = dict(alpha=sc.alpha, lam=sc.lam, tau=sc.tau, tv_iters=sc.tv_iters)
+        ps_sk, t_sk = psnr_vs_time(torch, fbpnp, plan, stage_of, b, xt, list(sc.stages), eta, **kw)
+        ps_fu, t_fu = psnr_vs_time(torch, fbpnp, plan, stage_of, b, xt, [(1, sc.full_iters)], eta, **kw)
+        p_ref = float(ps_fu[-1])
+
+        def first(ps, ts, target):
+            idx = np.nonzero(ps >= target)[0]
+            return None if len(idx) == 0 else round(float(ts[idx[0]]), 4)
+
+        # projector work per iteration: forward and matched back-projection, every view
+        work = {f: 2e-9 * plan.stage_info(stage_of[f]).samples_all_views for f in factors}
+        w_sk = np.cumsum([work[f] for f, n in sc.stages for _ in range(n)])
+        w_fu = np.cumsum([work[1]] * sc.full_iters)
+        res = {"views": V, "bins": B, "angle_range_deg": round(float(np.degrees(sc.angle_range)), 1), "i0": sc.i0,
+               "pnp_fista_final_psnr_db": round(p_ref, 3)}
+        for key, ps, ts, ws in (("ms2g_two_stage", ps_sk, t_sk, w_sk), ("pnp_fista", ps_fu, t_fu, w_fu)):
+            res[key] = {"iterations": int(len(ps)), "final_psnr_db": round(float(ps[-1]), 3),
+                        "max_psnr_db": round(float(ps.max()), 3), "total_ms": round(float(ts[-1]), 4),
+                        **{f"ms_to_ref_minus_{d}": first(ps, ts, p_ref - d) for d in (0.1, 0.5, 1.0)},
+                        **{f"gsamples_to_ref_minus_{d}": first(ps, ws, p_ref - d) for d in (0.1, 0.5, 1.0)},
+                        "psnr_curve_every_10": [round(float(v), 2) for v in ps[9::10]]}
+        for d in (0.1, 0.5, 1.0):
+            for unit, tag in (("ms", "speedup"), ("gsamples", "work_ratio")):
+                a_ = res["ms2g_two_stage"][f"{unit}_to_ref_minus_{d}"]
+                b_ = res["pnp_fista"][f"{unit}_to_ref_minus_{d}"]
+                res[f"{tag}_to_ref_minus_{d}"] = None if (a_ is None or b_ is None) else round(b_ / a_, 3)
+        out[name] = res
+        log(f"scenario {name}: {res}")
+        plan.close()
     return out
 
 

@@ -36,15 +36,17 @@ import numpy as np
 # geometry and workloads (plain descriptions)
 # ----------------------------------------------------------------------------------
 
-def fan_geometry(n: int, n_views: int, n_bins: int | None = None, angle_range: float = 2 * math.pi) -> dict:
-    """Geometry parameters for an n x n grid of 1 mm pixels."""
+def fan_geometry(n: int, n_views: int, n_bins: int | None = None, angle_range: float = 2 * math.pi,
+                 iso_pitch_px: float = 1.0) -> dict:
+    """Geometry parameters for an n x n grid of 1 mm pixels; a detector bin spans
+    iso_pitch_px pixels at the isocentre."""
     h = 1.0
     sod = 7.8125 * n * h
     sdd = 2.0 * sod
     return dict(
         nx=n, ny=n, pixel_mm=h, n_views=n_views,
         n_bins=int(round(1.5 * n)) if n_bins is None else n_bins,
-        sod_mm=sod, sdd_mm=sdd, det_pitch_mm=h * sdd / sod, det_offset_mm=0.0,
+        sod_mm=sod, sdd_mm=sdd, det_pitch_mm=iso_pitch_px * h * sdd / sod, det_offset_mm=0.0,
         angle0_rad=0.0, angle_step_rad=angle_range / n_views,
     )
 
@@ -132,6 +134,46 @@ BATCH_WORKLOADS = {
 }
 
 
+@dataclass
+class Scenario:
+    """One of the paper's experiments (Sec. 3): a 256 x 256 disk phantom, fan beam with 228
+    bins covering the field of view, Poisson transmission data at incident count i0, and the
+    two-stage sketch schedule (f = 4, then f = 2) against full-gradient PnP-FISTA."""
+    name: str
+    n_views: int
+    angle_range: float
+    i0: float
+    n: int = 256
+    n_bins: int = 228
+    n_disks: int = 10
+    mu0: float = 0.02           # 1/mm per unit density (about water)
+    stages: tuple = ((4, 25), (2, 75))
+    full_iters: int = 100
+    lam: float = 0.01
+    tv_iters: int = 5
+    tau: float = 0.125
+    alpha: float = 1.0
+    seed_base: int = 5
+
+    @property
+    def geometry(self) -> dict:
+        return fan_geometry(self.n, self.n_views, self.n_bins, self.angle_range, self.n / self.n_bins)
+
+    def phantom(self) -> np.ndarray:
+        return rasterise(random_disks(1000 * self.seed_base, self.n_disks, self.n), self.n).astype(np.float32)
+
+    def data(self, ax: np.ndarray) -> np.ndarray:
+        """Log transmission data (density units) for line integrals ax of the phantom."""
+        return transmission_data(ax, self.i0, self.mu0, 2000 * self.seed_base + self.n_views)
+
+
+SCENARIOS = {
+    "sparse_view": Scenario("sparse_view", 90, 2 * math.pi, 10 ** 5.5),
+    "low_dose": Scenario("low_dose", 360, 2 * math.pi, 10 ** 3.5),
+    "limited_angle": Scenario("limited_angle", 90, math.pi, 10 ** 5.5),
+}
+
+
 def momentum_table(T: int, fista: bool = True) -> np.ndarray:
     """a_t for t = 1..T: (t-1)/(t+3) for the FISTA-type sequence of Sec. 3, else 0."""
     t = np.arange(1, T + 1, dtype=np.float64)
@@ -187,6 +229,32 @@ def rasterise(e: Ellipses, n: int, pixel_mm: float = 1.0, sub: int = 4) -> np.nd
         inside = (u / e.a[i]) ** 2 + (v / e.b[i]) ** 2 <= 1.0
         img[r_lo:r_hi + 1, c_lo:c_hi + 1] += e.rho[i] * inside.mean(axis=(2, 3))
     return img
+
+
+def random_disks(seed: int, count: int, n: int, pixel_mm: float = 1.0) -> Ellipses:
+    """A disk phantom: a background disk of radius 0.85 R and density 0.4, and `count`
+    disks of various sizes inside it (radius uniform in [0.03 R, 0.2 R], centre uniform in
+    the disc of radius 0.55 R, density uniform in [0.1, 0.6]); densities add."""
+    rng = np.random.default_rng(seed)
+    R = 0.5 * n * pixel_mm
+    rad = 0.55 * R * np.sqrt(rng.random(count))
+    ang = 2 * np.pi * rng.random(count)
+    r = rng.uniform(0.03 * R, 0.2 * R, count)
+    rho = rng.uniform(0.1, 0.6, count)
+    cx = np.concatenate([[0.0], rad * np.cos(ang)])
+    cy = np.concatenate([[0.0], rad * np.sin(ang)])
+    rr = np.concatenate([[0.85 * R], r])
+    return Ellipses(cx, cy, rr, rr.copy(), np.zeros(count + 1), np.concatenate([[0.4], rho]))
+
+
+def transmission_data(ax: np.ndarray, i0: float, mu0: float, seed: int) -> np.ndarray:
+    """Poisson transmission measurement and its log, in the phantom's density units:
+    counts ~ Poisson(I0 exp(-mu0 Ax)), b = -log(max(counts, 0.5) / I0) / mu0
+    (ax: line integrals of the density image, mm; mu0: attenuation per unit density, 1/mm;
+    a zero count is read as half a count)."""
+    ax = np.asarray(ax, dtype=np.float64)
+    counts = np.random.default_rng(seed).poisson(i0 * np.exp(-mu0 * ax)).astype(np.float64)
+    return -np.log(np.maximum(counts, 0.5) / i0) / mu0
 
 
 def texture(seed: int, n: int, std: float = 0.02, smooth_px: float = 2.0) -> np.ndarray:
