@@ -90,6 +90,8 @@ def _load():
         lib.orc_grad.argtypes = [gp, i32, dp, dp, ip, i32, d, dp]
         lib.orc_tv_prox.argtypes = [dp, i32, i32, d, i32, d, dp]
         lib.orc_pnp_run.argtypes = [gp, i32, ip, ip, ip, ip, dp, dp, dp, d, d, i32, d, dp, dp, dp, dp]
+        lib.orc_grad_vr.argtypes = [gp, i32, dp, dp, ip, i32, d, dp, dp]
+        lib.orc_pnp_run_vr.argtypes = [gp, i32, ip, ip, ip, ip, dp, ip, dp, dp, d, d, i32, d, dp, dp, dp, dp]
         lib.orc_power_lipschitz.argtypes = [gp, i32, i32]
         lib.orc_power_lipschitz.restype = d
         lib.orc_psnr.argtypes = [dp, dp, ctypes.c_size_t]
@@ -192,6 +194,18 @@ def grad(g: Geometry, y, b, f: int = 1, views=None, sigma: float = 1.0) -> np.nd
     return out
 
 
+def grad_vr(g: Geometry, y, b, y_snap, f: int = 1, views=None, sigma: float = 1.0) -> np.ndarray:
+    """Variance-reduced (SVRG) estimator over view subsets: grad(y; M) - grad(y_snap; M)
+    + grad(y_snap; all views), the minibatch terms scaled by sigma."""
+    y, b, ys = _f64(y), _f64(b), _f64(y_snap)
+    assert y.shape == (g.ny, g.nx) and ys.shape == y.shape and b.shape == (g.n_views, g.n_bins)
+    v, vp = _views(views)
+    n_sel = g.n_views if v is None else len(v)
+    out = np.zeros((g.ny, g.nx))
+    _load().orc_grad_vr(ctypes.byref(g.c()), f, _dp(y), _dp(b), vp, n_sel, sigma, _dp(ys), _dp(out))
+    return out
+
+
 def tv_prox(z, lam: float, n_iter: int = 5, tau: float = 0.125) -> np.ndarray:
     """Denoiser D: n_iter Chambolle dual-projection steps for isotropic TV (Sec. 2.1, after Eq. (5))."""
     z = _f64(z)
@@ -202,10 +216,12 @@ def tv_prox(z, lam: float, n_iter: int = 5, tau: float = 0.125) -> np.ndarray:
 
 
 def pnp_run(g: Geometry, b, schedule, eta, a, alpha: float = 1.0, lam: float = 0.01,
-            tv_iters: int = 5, tau: float = 0.125, x0=None, history: bool = False):
+            tv_iters: int = 5, tau: float = 0.125, x0=None, history: bool = False, vr=None):
     """PnP-MS2G (Sec. 2.1, Algorithm 1) for T iterations.
 
     schedule: list of (f, views or None, sigma) per iteration; eta, a: length-T arrays.
+    vr (optional): gradient mode per iteration, 0 minibatch, 1 snapshot (full-view
+    gradient, remembered), 2 variance-reduced against the last snapshot of the same f.
     Returns x_T, or (x_T, history[T, ny, nx]) when history is True."""
     T = len(schedule)
     b = _f64(b)
@@ -222,9 +238,22 @@ def pnp_run(g: Geometry, b, schedule, eta, a, alpha: float = 1.0, lam: float = 0
     xo = np.zeros((g.ny, g.nx))
     hist = np.zeros((T, g.ny, g.nx)) if history else None
     ip = lambda arr: arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
-    _load().orc_pnp_run(ctypes.byref(g.c()), T, ip(factor), ip(views), ip(off), ip(n_sel), _dp(sigma),
-                        _dp(eta), _dp(a), alpha, lam, tv_iters, tau, _dp(b), _dp(x0), _dp(xo),
-                        _dp(hist) if history else None)
+    if vr is None:
+        _load().orc_pnp_run(ctypes.byref(g.c()), T, ip(factor), ip(views), ip(off), ip(n_sel), _dp(sigma),
+                            _dp(eta), _dp(a), alpha, lam, tv_iters, tau, _dp(b), _dp(x0), _dp(xo),
+                            _dp(hist) if history else None)
+    else:
+        mode = np.ascontiguousarray(vr, dtype=np.int32)
+        assert mode.shape == (T,) and set(mode.tolist()) <= {0, 1, 2}
+        snap_f = None
+        for t in range(T):  # a variance-reduced step needs a snapshot of its own stage
+            if mode[t] == 1:
+                snap_f = factor[t]
+            elif mode[t] == 2 and snap_f != factor[t]:
+                raise ValueError(f"iteration {t}: variance-reduced step without a snapshot at f = {factor[t]}")
+        _load().orc_pnp_run_vr(ctypes.byref(g.c()), T, ip(factor), ip(views), ip(off), ip(n_sel), _dp(sigma),
+                               ip(mode), _dp(eta), _dp(a), alpha, lam, tv_iters, tau, _dp(b), _dp(x0), _dp(xo),
+                               _dp(hist) if history else None)
     return (xo, hist) if history else xo
 
 

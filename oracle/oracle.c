@@ -416,6 +416,75 @@ void orc_pnp_run(const orc_geom* g, int T, const int32_t* factor, const int32_t*
 }
 
 /* ------------------------------------------------------------------------- */
+/* Variance-reduced minibatch gradient (Sec. 2.1, the estimators named after  */
+/* Eq. (7); here SVRG over view subsets)                                      */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * G = g_M(y) - g_M(y_snap) + g(y_snap): the minibatch gradient of orc_grad at y,
+ * corrected by the same minibatch at the snapshot y_snap and the full-view
+ * gradient there (sigma scales both minibatch terms).
+ */
+void orc_grad_vr(const orc_geom* g, int f, const double* y, const double* b, const int32_t* views, int n_sel,
+                 double sigma, const double* y_snap, double* grad) {
+    size_t n = (size_t)g->nx * g->ny;
+    double* gs = (double*)malloc(n * sizeof(double));
+    double* gf = (double*)malloc(n * sizeof(double));
+    orc_grad(g, f, y, b, views, n_sel, sigma, grad);
+    orc_grad(g, f, y_snap, b, views, n_sel, sigma, gs);
+    orc_grad(g, f, y_snap, b, NULL, g->n_views, 1.0, gf);
+    for (size_t i = 0; i < n; ++i) grad[i] = grad[i] - gs[i] + gf[i];
+    free(gs);
+    free(gf);
+}
+
+/*
+ * orc_pnp_run with a gradient mode per iteration: mode[t] = 0 the minibatch
+ * gradient as in orc_pnp_run; 1 a snapshot: y_snap = y_{t-1} and the full-view
+ * gradient there (the step's own gradient); 2 the variance-reduced gradient of
+ * orc_grad_vr against the last snapshot (which must use the same factor).
+ */
+void orc_pnp_run_vr(const orc_geom* g, int T, const int32_t* factor, const int32_t* views,
+                    const int32_t* view_off, const int32_t* n_sel, const double* sigma, const int32_t* mode,
+                    const double* eta, const double* a, double alpha, double lambda, int tv_iters, double tau,
+                    const double* b, const double* x0, double* x_out, double* history) {
+    size_t n = (size_t)g->nx * g->ny;
+    double* x_prev = (double*)malloc(n * sizeof(double));
+    double* y = (double*)malloc(n * sizeof(double));
+    double* z = (double*)malloc(n * sizeof(double));
+    double* x = (double*)malloc(n * sizeof(double));
+    double* gr = (double*)malloc(n * sizeof(double));
+    double* y_snap = (double*)calloc(n, sizeof(double));
+    memcpy(x_prev, x0, n * sizeof(double));
+    memcpy(y, x0, n * sizeof(double));
+    for (int t = 0; t < T; ++t) {
+        const int32_t* vw = views ? views + view_off[t] : NULL;
+        int ns = views ? n_sel[t] : g->n_views;
+        if (mode[t] == 1) {
+            memcpy(y_snap, y, n * sizeof(double));
+            orc_grad(g, factor[t], y, b, NULL, g->n_views, 1.0, gr);
+        } else if (mode[t] == 2) {
+            orc_grad_vr(g, factor[t], y, b, vw, ns, sigma[t], y_snap, gr);
+        } else {
+            orc_grad(g, factor[t], y, b, vw, ns, sigma[t], gr);
+        }
+        for (size_t i = 0; i < n; ++i) z[i] = y[i] - eta[t] * gr[i];
+        orc_tv_prox(z, g->nx, g->ny, lambda, tv_iters, tau, x);
+        for (size_t i = 0; i < n; ++i) x[i] = (1.0 - alpha) * z[i] + alpha * x[i];
+        for (size_t i = 0; i < n; ++i) y[i] = x[i] + a[t] * (x[i] - x_prev[i]);
+        if (history) memcpy(history + (size_t)t * n, x, n * sizeof(double));
+        memcpy(x_prev, x, n * sizeof(double));
+    }
+    memcpy(x_out, x_prev, n * sizeof(double));
+    free(x_prev);
+    free(y);
+    free(z);
+    free(x);
+    free(gr);
+    free(y_snap);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Lipschitz constant of the sketched data term (step eta = 1/L, Sec. 3)      */
 /* ------------------------------------------------------------------------- */
 
