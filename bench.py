@@ -373,14 +373,18 @@ def main() -> int:
                 t += 1
         return out
 
-    def make_steps(sched, hist=None, events=None):
+    def make_steps(sched, hist=None, events=None, vr=None, snaps=None):
+        """pnp_step arguments; vr (optional): per-step variance-reduction mode, with
+        snaps[f] = (snapshot projection, snapshot coarse gradient) per stage."""
         steps = []
         for t, (f, s, a_t) in enumerate(sched):
-            views = None if s is None else subsets[s]
-            sigma = 1.0 if s is None else float(n_sub)
+            mode = 0 if vr is None else vr[t]
+            views = None if (s is None or mode == 1) else subsets[s]
+            sigma = 1.0 if views is None else float(n_sub)
+            sp, sg = (None, None) if mode == 0 else snaps[f]
             steps.append(fbpnp.pnp_args(plan, stage_of[f], b, y, x, x, y, eta[f], a_t, views, sigma, w.alpha, w.lam,
                                         w.tau, w.tv_iters, None if hist is None else hist[t],
-                                        None if events is None else events[t]))
+                                        None if events is None else events[t], mode, sp, sg))
         return steps
 
     sk_sched = schedule(w.stages, 3000 * w.seed_base, n_sub)
@@ -525,13 +529,18 @@ def main() -> int:
 
 def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x, y, xt, T, tune_cache):
     """Per-iteration PSNR (from an iterate history) against cumulative GPU time, for the
-    sketched schedule, full-gradient PnP-FISTA and full-resolution PnP-SGD."""
+    sketched schedule (minibatch and variance-reduced gradients), full-gradient PnP-FISTA
+    and full-resolution PnP-SGD."""
     N = w.n
     npix = N * N
     ref = torch.from_numpy(xt).cuda().reshape(1, -1).double()
     peak = float(xt.max() - xt.min())
 
-    def run(stages, n_sub_used, seed, t_offset=0, x_init=None):
+    V, B = w.n_views, w.n_bins
+    snaps = {f: (torch.zeros(V * B, device="cuda"), torch.zeros((N // f) ** 2, device="cuda"))
+             for f, _ in w.stages}
+
+    def run(stages, n_sub_used, seed, t_offset=0, x_init=None, vr=False):
         # each method runs with the launch configurations tuned for its view count
         plan.autotune(n_sel=w.n_views // n_sub_used if n_sub_used else w.n_views, cache_path=tune_cache)
         sched = schedule(stages, seed, n_sub_used, True, t_offset)
@@ -541,7 +550,11 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
         for f, n in stages:
             stage_blocks.append((t, t + n))
             t += n
-        graphs = [fbpnp.Graph(plan, make_steps(sched[a:b], hist[a:b])) for a, b in stage_blocks]
+        # variance reduction: an epoch of n_sub iterations opens with a full-view snapshot step
+        modes = [1 if (i - a) % n_sub_used == 0 else 2 for a, bnd in stage_blocks for i in range(a, bnd)] if vr \
+            else None
+        graphs = [fbpnp.Graph(plan, make_steps(sched[a:b], hist[a:b], None, None if modes is None else modes[a:b],
+                                               snaps)) for a, b in stage_blocks]
         if x_init is None:
             x.zero_()
             y.zero_()
@@ -578,6 +591,7 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
     ps_full, t_full, _ = run([(1, T)], 0, seed)
     ps_sgd, t_sgd, _ = run([(1, T)], w.n_subsets, seed + 1)
     ps_sk, t_sk, fin = run(w.stages, w.n_subsets, seed)
+    ps_vr, t_vr, _ = run(w.stages, w.n_subsets, seed, vr=True)
     # extend the sketched run's final stage (same subset stream rule) up to 240 iterations
     ext_p, ext_t = [ps_sk], [t_sk]
     p_star = float(ps_full[-1])
@@ -594,8 +608,8 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
         return None if len(idx) == 0 else round(float(ts[idx[0]]), 4)
 
     out = {"p_star_db": round(p_star, 3), "definition": "P* = PSNR of full-gradient PnP-FISTA after 60 iterations"}
-    for name, ps, ts in (("sketched_ms2g", ps_sk_all, t_sk_all), ("full_pnp_fista", ps_full, t_full),
-                         ("full_res_pnp_sgd", ps_sgd, t_sgd)):
+    for name, ps, ts in (("sketched_ms2g", ps_sk_all, t_sk_all), ("sketched_ms2g_svrg", ps_vr, t_vr),
+                         ("full_pnp_fista", ps_full, t_full), ("full_res_pnp_sgd", ps_sgd, t_sgd)):
         out[name] = {
             "iterations": int(len(ps)), "final_psnr_db": round(float(ps[-1]), 3),
             "max_psnr_db": round(float(ps.max()), 3), "total_ms": round(float(ts[-1]), 4),

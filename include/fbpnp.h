@@ -179,6 +179,17 @@ fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_
  * of its denoiser kernel (hipExtLaunchKernelGGL start/stop events), so their
  * elapsed time is the kernel's own duration. A NULL entry is skipped. The
  * caller owns the events. fb_graph_create ignores them.
+ * Variance-reduced gradients (SVRG over view subsets; the estimators named
+ * after Eq. (7)), by vr_mode:
+ *   0  the minibatch gradient above (snap_proj, snap_grad unused);
+ *   1  snapshot: every view (views NULL, n_sel = n_views, sigma 1); the step
+ *      is the full-gradient step, and it also stores the snapshot's projection
+ *      A_s v into snap_proj (device [n_views][n_bins]) and its coarse gradient
+ *      A_s^T (A_s v - b) into snap_grad (device [nys][nxs] of the stage);
+ *   2  G = sigma (M A_s)^T (M A_s v - M snap_proj) + snap_grad, i.e.
+ *      g_M(y) - g_M(y_snap) + g(y_snap) with the last snapshot of this stage.
+ * A snapshot's buffers belong to one stage; take a new snapshot when the stage
+ * changes.
  */
 typedef struct fb_pnp_args {
     int32_t stage;
@@ -196,6 +207,9 @@ typedef struct fb_pnp_args {
     int32_t next_stage;
     int32_t prepared;
     hipEvent_t const* events;
+    int32_t vr_mode;
+    float* snap_proj;
+    float* snap_grad;
 } fb_pnp_args;
 fb_status pnp_step(const fb_plan* plan, const fb_pnp_args* args, hipStream_t stream);
 
@@ -291,7 +305,7 @@ fb_status tv_prox_vjp(const float* z, const float* xbar, float* zbar, int nx, in
 /*
  * pnp_step_vjp: reverse mode of one pnp_step (Sec. 2.1, Algorithm 1) at the
  * inputs in args (b, y_prev, views, sigma, eta, alpha, a_t, lambda, tau,
- * tv_iters; x_out, y_out and history are ignored). Given the adjoints
+ * tv_iters; x_out, y_out and history are ignored; vr_mode must be 0). Given the adjoints
  * xbar = dL/dx_t and ybar = dL/dy_t (ybar may be NULL for 0), computes
  *   xbar_prev = dL/dx_{t-1} = -a_t ybar            (may be NULL)
  *   ybar_prev = dL/dy_{t-1} = zbar - eta H zbar,    zbar = J_relax^T (xbar + (1 + a_t) ybar)

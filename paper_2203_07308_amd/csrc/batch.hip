@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_fp_batch(const SliceDesc* __restrict__ 
     const int n_sel = dcdiv(D.n_views, view_step);
     dev::fp_body<true, SEG>(w.local, S.rays, D.n_bins, dcdiv(D.n_bins, R) * R, nullptr, view0, view_step, n_sel,
                             D.n_views, S.lines, S.ly_off, S.line_bytes, S.pitch_x, S.pitch_y, S.nxs, S.nys,
-                            b + D.sino_off, D.resid);
+                            b + D.sino_off, D.resid, nullptr);
 }
 
 template <int VG, int PX>

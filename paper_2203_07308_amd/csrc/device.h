@@ -91,12 +91,14 @@ __device__ __forceinline__ int wave_max(int v) {
 
 // Work-group blk (256 threads) of a projection; view i of the selection is
 // views[i], or view0 + i * view_step without a list.
+// proj_out (optional): the projection itself, before b is subtracted, stored
+// by view ([n_views][n_bins]).
 template <bool kResid, int SEG>
 __device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays, int n_bins, int bins_padded,
                                         const int32_t* __restrict__ views, int view0, int view_step, int n_sel,
                                         int n_views, const float* __restrict__ lines, int ly_off, int line_bytes,
                                         int pitch_x, int pitch_y, int nxs, int nys, const float* __restrict__ b,
-                                        float* __restrict__ y) {
+                                        float* __restrict__ y, float* __restrict__ proj_out = nullptr) {
     constexpr int R = 64 / SEG;  // rays per wavefront; SEG lanes share one ray
     const int lane = threadIdx.x & 63;
     const int wave = (blk * 256 + (int)threadIdx.x) >> 6;
@@ -154,8 +156,10 @@ __device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays
     if (active && seg == 0) {
         float val = 0.f;
         if (valid) {
-            val = acc * r.len;
-            if (kResid) val -= b[(size_t)v * n_bins + j];
+            // the residual as an explicit fused multiply-add, so every kernel rounds it alike
+            const float p = acc * r.len;
+            if (proj_out) proj_out[(size_t)v * n_bins + j] = p;
+            val = kResid ? fmaf(acc, r.len, -b[(size_t)v * n_bins + j]) : p;
         }
         y[(size_t)i * n_bins + j] = val;
     }
@@ -267,12 +271,16 @@ __device__ __forceinline__ void bp_class(const ViewRec& vr, const float4* __rest
 }
 
 // Work-group blk (64 VG threads) of a backprojection; views as in fp_body.
+// Fused form, optional extras: mu (a coarse gradient [nys][nxs]) enters the
+// step as z = y_prev - U(scale g + mu_scale mu); g_out receives g itself.
 template <int VG, int PX, bool kFused>
 __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays, const ViewRec* __restrict__ vrec,
                                         int n_bins, const int32_t* __restrict__ views, int view0, int view_step,
                                         int n_sel, int n_views, const float* __restrict__ y, int nxs, int nys,
                                         int blocks_x, float scale, float* __restrict__ xo, int f, int nx,
-                                        const float* __restrict__ yprev, float* __restrict__ z) {
+                                        const float* __restrict__ yprev, float* __restrict__ z,
+                                        const float* __restrict__ mu = nullptr, float mu_scale = 0.f,
+                                        float* __restrict__ g_out = nullptr) {
     constexpr int BW = 8 * PX;  // block width in pixels
     __shared__ float4 stage[VG][kStageRays];
     __shared__ float red[VG > 1 ? VG - 1 : 1][PX * PX][64];
@@ -371,10 +379,14 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
                 xo[(size_t)R * nxs + C] = scale * acc[dr][dc];
             } else {
                 // z = y_prev - (eta sigma / f^2) g on the f x f block of (R, C)
-                const float sg = scale * acc[dr][dc];
+                // (explicit fused multiply-adds: every kernel rounds this the same way)
+                const size_t q = (size_t)R * nxs + C;
+                const float g = acc[dr][dc];
+                if (g_out) g_out[q] = g;
+                const float ms = mu ? mu_scale * mu[q] : 0.f;
                 for (int a = 0; a < f; ++a) {
                     const size_t row = (size_t)(f * R + a) * nx + (size_t)f * C;
-                    for (int bb = 0; bb < f; ++bb) z[row + bb] = yprev[row + bb] - sg;
+                    for (int bb = 0; bb < f; ++bb) z[row + bb] = fmaf(-scale, g, yprev[row + bb] - ms);
                 }
             }
         }

@@ -115,8 +115,9 @@ StageLines stage_lines(const fb_plan* p, int stage);
 // Pooling D_f of x (ny x nx) into the stage's line images.
 fb_status launch_prepare(const fb_plan* p, int stage, const float* x, int nx, int f, hipStream_t s);
 // Projection of the selected views from the stage's line images (minus b when resid).
+// proj_out (optional): the raw projection by view, [n_views][n_bins].
 fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* views, int n_sel, const float* b,
-                    float* y, hipStream_t s);
+                    float* y, hipStream_t s, float* proj_out = nullptr);
 // Backprojection: xo = scale A_s^T y (coarse), or fused: z = yprev - scale D^T-replicate(A_s^T y).
 fb_status launch_bp(const fb_plan* p, int stage, const float* y, const int32_t* views, int n_sel, float scale,
                     float* xo, const float* yprev, float* z, bool fused, hipStream_t s);

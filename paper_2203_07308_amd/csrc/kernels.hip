@@ -41,9 +41,10 @@ __global__ __launch_bounds__(256) void k_fp(const RayRec* __restrict__ rays, int
                                             const int32_t* __restrict__ views, int n_sel, int n_views,
                                             const float* __restrict__ lines, int ly_off, int line_bytes,
                                             int pitch_x, int pitch_y, int nxs, int nys,
-                                            const float* __restrict__ b, float* __restrict__ y) {
+                                            const float* __restrict__ b, float* __restrict__ y,
+                                            float* __restrict__ proj_out) {
     dev::fp_body<kResid, SEG>(blockIdx.x, rays, n_bins, bins_padded, views, 0, 1, n_sel, n_views, lines, ly_off,
-                              line_bytes, pitch_x, pitch_y, nxs, nys, b, y);
+                              line_bytes, pitch_x, pitch_y, nxs, nys, b, y, proj_out);
 }
 
 template <int VG, int PX, bool kFused>
@@ -51,9 +52,11 @@ __global__ __launch_bounds__(64 * VG) void k_bp(const RayRec* __restrict__ rays,
                                                 int n_bins, const int32_t* __restrict__ views, int n_sel,
                                                 int n_views, const float* __restrict__ y, int nxs, int nys,
                                                 int blocks_x, float scale, float* __restrict__ xo, int f, int nx,
-                                                const float* __restrict__ yprev, float* __restrict__ z) {
+                                                const float* __restrict__ yprev, float* __restrict__ z,
+                                                const float* __restrict__ mu, float mu_scale,
+                                                float* __restrict__ g_out) {
     dev::bp_body<VG, PX, kFused>(blockIdx.x, rays, vrec, n_bins, views, 0, 1, n_sel, n_views, y, nxs, nys, blocks_x,
-                                 scale, xo, f, nx, yprev, z);
+                                 scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
 }
 
 template <int T, int H, int NT>
@@ -236,7 +239,7 @@ fb_launch_config plan_config(const fb_plan* p, int stage, int n_sel) {
 }
 
 fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* views, int n_sel, const float* b,
-                    float* y, hipStream_t s) {
+                    float* y, hipStream_t s, float* proj_out) {
     const Stage& st = p->stages[stage];
     StageLines L = stage_lines(p, stage);
     const int nb = p->g.n_bins;
@@ -246,7 +249,7 @@ fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* view
     const int blocks = cdiv(n_sel * (bp / rays_per_wave), 4);
 #define FB_FP(RES, SG)                                                                                        \
     FB_LAUNCH((k_fp<RES, SG>), dim3(blocks), dim3(256), s, st.rays, nb, bp, views, n_sel, p->g.n_views, L.lx,   \
-              L.ly_off, L.bytes, st.pitch_x, st.pitch_y, st.nxs, st.nys, b, y)
+              L.ly_off, L.bytes, st.pitch_x, st.pitch_y, st.nxs, st.nys, b, y, proj_out)
     if (resid) {
         if (seg == 8) FB_FP(true, 8);
         else if (seg == 4) FB_FP(true, 4);
@@ -264,7 +267,8 @@ fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* view
 
 template <bool kFused>
 static fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const int32_t* views, int n_sel,
-                             float scale, float* xo, const float* yprev, float* z, hipStream_t s) {
+                             float scale, float* xo, const float* yprev, float* z, hipStream_t s,
+                             const float* mu = nullptr, float mu_scale = 0.f, float* g_out = nullptr) {
     const Stage& st = p->stages[stage];
     const fb_launch_config c = plan_config(p, stage, n_sel);
     const int px = c.bp_px, vg = c.bp_vg;
@@ -273,7 +277,7 @@ static fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const 
     const int nb = p->g.n_bins, f = st.f, nx = p->g.nx;
 #define FB_BP(VG, PX)                                                                                         \
     FB_LAUNCH((k_bp<VG, PX, kFused>), dim3(nblk), dim3(64 * VG), s, st.rays, st.vrec, nb, views, n_sel,         \
-              p->g.n_views, y, st.nxs, st.nys, bxs, scale, xo, f, nx, yprev, z)
+              p->g.n_views, y, st.nxs, st.nys, bxs, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out)
 #define FB_BP_VG(PX)           \
     switch (vg) {              \
         case 1: FB_BP(1, PX); break;  \
@@ -554,18 +558,29 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
     if (a->next_stage < -1 || a->next_stage >= (int)p->stages.size())
         return fail(FB_EINVAL, "pnp_step: next_stage out of range");
     if (a->prepared != 0 && a->prepared != 1) return fail(FB_EINVAL, "pnp_step: prepared must be 0 or 1");
+    if (a->vr_mode < 0 || a->vr_mode > 2) return fail(FB_EINVAL, "pnp_step: vr_mode must be 0, 1 or 2");
+    if (a->vr_mode && (!a->snap_proj || !a->snap_grad))
+        return fail(FB_EINVAL, "pnp_step: variance-reduced modes need snap_proj and snap_grad");
+    if (a->vr_mode == 1 && a->n_sel != p->g.n_views)
+        return fail(FB_ESUBSET, "pnp_step: a snapshot step uses every view");
     const Stage& S = p->stages[a->stage];
     const int nx = p->g.nx, ny = p->g.ny;
     if (!a->prepared && (st = launch_prepare(p, a->stage, a->y_prev, nx, S.f, stream)) != FB_OK) return st;
+    // variance-reduced modes: 1 records the snapshot's projection and coarse
+    // gradient; 2 projects against the snapshot's projection and adds its gradient
+    const bool snap = a->vr_mode == 1, vr = a->vr_mode == 2;
     {
         TimedLaunch tl(a->events, 0);
-        if ((st = launch_fp(p, a->stage, true, a->views, a->n_sel, a->b, p->resid, stream)) != FB_OK) return st;
+        if ((st = launch_fp(p, a->stage, true, a->views, a->n_sel, vr ? a->snap_proj : a->b, p->resid, stream,
+                            snap ? a->snap_proj : nullptr)) != FB_OK)
+            return st;
     }
     const float step = a->eta * a->sigma / (float)(S.f * S.f);
     {
         TimedLaunch tl(a->events, 2);
         if ((st = launch_bp_t<true>(p, a->stage, p->resid, a->views, a->n_sel, step, nullptr, a->y_prev, p->zbuf,
-                                    stream)) != FB_OK)
+                                    stream, vr ? a->snap_grad : nullptr, a->eta / (float)(S.f * S.f),
+                                    snap ? a->snap_grad : nullptr)) != FB_OK)
             return st;
     }
     PoolTarget pt;

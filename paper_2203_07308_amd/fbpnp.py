@@ -61,6 +61,7 @@ class PnpArgs(ctypes.Structure):
         ("x_out", ctypes.c_void_p), ("y_out", ctypes.c_void_p), ("history", ctypes.c_void_p),
         ("next_stage", ctypes.c_int32), ("prepared", ctypes.c_int32),
         ("events", ctypes.POINTER(ctypes.c_void_p)),
+        ("vr_mode", ctypes.c_int32), ("snap_proj", ctypes.c_void_p), ("snap_grad", ctypes.c_void_p),
     ]
 
 
@@ -303,9 +304,12 @@ def tv_prox(z: torch.Tensor, x: torch.Tensor, lam: float, n_iter: int = 5, tau: 
 def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float, a_t: float,
              views: torch.Tensor | None = None, sigma: float = 1.0, alpha: float = 1.0, lam: float = 0.01,
              tau: float = 0.125, tv_iters: int = 5, history: torch.Tensor | None = None,
-             events=None) -> PnpArgs:
+             events=None, vr_mode: int = 0, snap_proj: torch.Tensor | None = None,
+             snap_grad: torch.Tensor | None = None) -> PnpArgs:
     """Arguments of one pnp_step. events: optional sequence of six torch.cuda.Event
-    (enable_timing=True) or None, recorded around the step's fp, bp and TV kernels."""
+    (enable_timing=True) or None, recorded around the step's fp, bp and TV kernels.
+    vr_mode 1 / 2 with snap_proj [n_views * n_bins] and snap_grad (the stage's coarse
+    image size): variance-reduced snapshot / step (see include/fbpnp.h)."""
     npix = plan.geom.nx * plan.geom.ny
     vp, n_sel = _views(plan, views)
     a = PnpArgs(stage, vp, n_sel, sigma, eta, alpha, a_t, lam, tau, tv_iters,
@@ -313,6 +317,11 @@ def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float
                 _ptr(y_prev, numel=npix, name="y_prev"), _ptr(x_prev, numel=npix, name="x_prev"),
                 _ptr(x_out, numel=npix, name="x_out"), _ptr(y_out, numel=npix, name="y_out"),
                 _ptr(history, numel=npix, name="history"), -1, 0)
+    if vr_mode:
+        nys, nxs = plan.coarse_shape(stage)
+        a.vr_mode = vr_mode
+        a.snap_proj = _ptr(snap_proj, numel=plan.geom.n_views * plan.geom.n_bins, name="snap_proj")
+        a.snap_grad = _ptr(snap_grad, numel=nxs * nys, name="snap_grad")
     if events is not None:
         if len(events) != 6:
             raise ValueError("events: need six entries (fp, bp, TV; begin and end)")
