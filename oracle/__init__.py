@@ -91,6 +91,13 @@ def _load():
         lib.orc_tv_prox.argtypes = [dp, i32, i32, d, i32, d, dp]
         lib.orc_pnp_run.argtypes = [gp, i32, ip, ip, ip, ip, dp, dp, dp, d, d, i32, d, dp, dp, dp, dp]
         lib.orc_grad_vr.argtypes = [gp, i32, dp, dp, ip, i32, d, dp, dp]
+        lib.orc_bicubic_matrix.argtypes = [i32, i32, dp]
+        lib.orc_sketch_down.argtypes = [i32, dp, i32, i32, i32, dp]
+        lib.orc_sketch_up.argtypes = [i32, dp, i32, i32, i32, dp]
+        lib.orc_grad_k.argtypes = [gp, i32, i32, dp, dp, ip, i32, d, dp]
+        lib.orc_pnp_run_k.argtypes = [gp, i32, i32, ip, ip, ip, ip, dp, dp, dp, d, d, i32, d, dp, dp, dp, dp]
+        lib.orc_power_lipschitz_k.argtypes = [gp, i32, i32, i32]
+        lib.orc_power_lipschitz_k.restype = d
         lib.orc_pnp_run_vr.argtypes = [gp, i32, ip, ip, ip, ip, dp, ip, dp, dp, d, d, i32, d, dp, dp, dp, dp]
         lib.orc_power_lipschitz.argtypes = [gp, i32, i32]
         lib.orc_power_lipschitz.restype = d
@@ -183,14 +190,42 @@ def up(v, f: int) -> np.ndarray:
     return x
 
 
-def grad(g: Geometry, y, b, f: int = 1, views=None, sigma: float = 1.0) -> np.ndarray:
+SKETCHES = {"pool": 0, "bicubic": 1}
+
+
+def bicubic_matrix(n: int, f: int) -> np.ndarray:
+    """The 1-D bicubic sketch (n / f x n): Keys' cubic kernel (a = -1/2) stretched by f,
+    half-sample reflection at the ends, rows normalised to 1 (Sec. 3, bicubic resizing)."""
+    S = np.zeros((n // f, n))
+    _load().orc_bicubic_matrix(n, f, _dp(S))
+    return S
+
+
+def sketch_down(x, f: int, sketch: str = "pool") -> np.ndarray:
+    x = _f64(x)
+    ny, nx = x.shape
+    v = np.zeros((ny // f, nx // f))
+    _load().orc_sketch_down(SKETCHES[sketch], _dp(x), nx, ny, f, _dp(v))
+    return v
+
+
+def sketch_up(v, f: int, sketch: str = "pool") -> np.ndarray:
+    """U = S^T (for pooling D^T: replicate and divide by f^2)."""
+    v = _f64(v)
+    nys, nxs = v.shape
+    x = np.zeros((nys * f, nxs * f))
+    _load().orc_sketch_up(SKETCHES[sketch], _dp(v), nxs, nys, f, _dp(x))
+    return x
+
+
+def grad(g: Geometry, y, b, f: int = 1, views=None, sigma: float = 1.0, sketch: str = "pool") -> np.ndarray:
     """Sketched minibatch gradient sigma * U (M A_s)^T (M A_s S y - M b) (Sec. 2.1, Eqs. (6)-(7))."""
     y, b = _f64(y), _f64(b)
     assert y.shape == (g.ny, g.nx) and b.shape == (g.n_views, g.n_bins)
     v, vp = _views(views)
     n_sel = g.n_views if v is None else len(v)
     out = np.zeros((g.ny, g.nx))
-    _load().orc_grad(ctypes.byref(g.c()), f, _dp(y), _dp(b), vp, n_sel, sigma, _dp(out))
+    _load().orc_grad_k(ctypes.byref(g.c()), SKETCHES[sketch], f, _dp(y), _dp(b), vp, n_sel, sigma, _dp(out))
     return out
 
 
@@ -216,7 +251,7 @@ def tv_prox(z, lam: float, n_iter: int = 5, tau: float = 0.125) -> np.ndarray:
 
 
 def pnp_run(g: Geometry, b, schedule, eta, a, alpha: float = 1.0, lam: float = 0.01,
-            tv_iters: int = 5, tau: float = 0.125, x0=None, history: bool = False, vr=None):
+            tv_iters: int = 5, tau: float = 0.125, x0=None, history: bool = False, vr=None, sketch: str = "pool"):
     """PnP-MS2G (Sec. 2.1, Algorithm 1) for T iterations.
 
     schedule: list of (f, views or None, sigma) per iteration; eta, a: length-T arrays.
@@ -239,10 +274,11 @@ def pnp_run(g: Geometry, b, schedule, eta, a, alpha: float = 1.0, lam: float = 0
     hist = np.zeros((T, g.ny, g.nx)) if history else None
     ip = lambda arr: arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
     if vr is None:
-        _load().orc_pnp_run(ctypes.byref(g.c()), T, ip(factor), ip(views), ip(off), ip(n_sel), _dp(sigma),
-                            _dp(eta), _dp(a), alpha, lam, tv_iters, tau, _dp(b), _dp(x0), _dp(xo),
-                            _dp(hist) if history else None)
+        _load().orc_pnp_run_k(ctypes.byref(g.c()), SKETCHES[sketch], T, ip(factor), ip(views), ip(off), ip(n_sel),
+                              _dp(sigma), _dp(eta), _dp(a), alpha, lam, tv_iters, tau, _dp(b), _dp(x0), _dp(xo),
+                              _dp(hist) if history else None)
     else:
+        assert sketch == "pool", "variance reduction is defined with the pooling sketch"
         mode = np.ascontiguousarray(vr, dtype=np.int32)
         assert mode.shape == (T,) and set(mode.tolist()) <= {0, 1, 2}
         snap_f = None
@@ -295,9 +331,9 @@ def pnp_vjp(g: Geometry, b, schedule, eta, a, xT_bar, alpha: float = 1.0, lam: f
     return x0_bar, eta_bar
 
 
-def power_lipschitz(g: Geometry, f: int = 1, n_iter: int = 100) -> float:
-    """L = ||A_s D_f||_2^2 by power iteration, for the step eta = 1/L (Sec. 3)."""
-    return float(_load().orc_power_lipschitz(ctypes.byref(g.c()), f, n_iter))
+def power_lipschitz(g: Geometry, f: int = 1, n_iter: int = 100, sketch: str = "pool") -> float:
+    """L = ||A_s S||_2^2 by power iteration, for the step eta = 1/L (Sec. 3)."""
+    return float(_load().orc_power_lipschitz_k(ctypes.byref(g.c()), SKETCHES[sketch], f, n_iter))
 
 
 def psnr(x, ref) -> float:

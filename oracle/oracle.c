@@ -284,6 +284,106 @@ void orc_up(const double* v, int nxs, int nys, int f, double* x) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Bicubic sketch (Sec. 3: resizing with bicubic interpolation)               */
+/* ------------------------------------------------------------------------- */
+
+/* Keys' cubic convolution kernel with a = -1/2. */
+static double keys(double s) {
+    const double a = -0.5, t = fabs(s);
+    if (t <= 1.0) return ((a + 2.0) * t - (a + 3.0)) * t * t + 1.0;
+    if (t < 2.0) return ((a * t - 5.0 * a) * t + 8.0 * a) * t - 4.0 * a;
+    return 0.0;
+}
+
+/* Half-sample symmetric reflection of an index into [0, n). */
+static int reflect(int i, int n) {
+    while (i < 0 || i >= n) {
+        if (i < 0) i = -1 - i;
+        if (i >= n) i = 2 * n - 1 - i;
+    }
+    return i;
+}
+
+/*
+ * The 1-D bicubic sketch, S (m x n, row-major, m = n / f). Output o sits at the
+ * input coordinate u = (o + 1/2) f - 1/2 (pixel centres aligned as when n
+ * pixels are resized to n / f); its weights are keys((i - u) / f) for the
+ * inputs i with |i - u| < 2 f (the kernel stretched by f against aliasing),
+ * folded into the image by half-sample reflection at both ends, then divided
+ * by their sum. f = 1 gives the identity.
+ */
+void orc_bicubic_matrix(int n, int f, double* S) {
+    const int m = n / f;
+    memset(S, 0, (size_t)m * n * sizeof(double));
+    for (int o = 0; o < m; ++o) {
+        const double u = (o + 0.5) * f - 0.5;
+        double sum = 0.0;
+        for (int i = (int)floor(u - 2.0 * f); i <= (int)ceil(u + 2.0 * f); ++i) {
+            const double w = keys((i - u) / f);
+            if (w == 0.0) continue;
+            S[(size_t)o * n + reflect(i, n)] += w;
+            sum += w;
+        }
+        for (int i = 0; i < n; ++i) S[(size_t)o * n + i] /= sum;
+    }
+}
+
+/* v = S x for the 2-D separable bicubic sketch (rows with S_x, columns with S_y). */
+static void bicubic_down(const double* x, int nx, int ny, int f, double* v) {
+    const int nxs = nx / f, nys = ny / f;
+    double* Sx = (double*)malloc((size_t)nxs * nx * sizeof(double));
+    double* Sy = (double*)malloc((size_t)nys * ny * sizeof(double));
+    double* t = (double*)calloc((size_t)ny * nxs, sizeof(double));
+    orc_bicubic_matrix(nx, f, Sx);
+    orc_bicubic_matrix(ny, f, Sy);
+    for (int r = 0; r < ny; ++r)
+        for (int C = 0; C < nxs; ++C)
+            for (int c = 0; c < nx; ++c) t[(size_t)r * nxs + C] += Sx[(size_t)C * nx + c] * x[(size_t)r * nx + c];
+    for (int R = 0; R < nys; ++R)
+        for (int C = 0; C < nxs; ++C) {
+            double acc = 0.0;
+            for (int r = 0; r < ny; ++r) acc += Sy[(size_t)R * ny + r] * t[(size_t)r * nxs + C];
+            v[(size_t)R * nxs + C] = acc;
+        }
+    free(Sx);
+    free(Sy);
+    free(t);
+}
+
+/* x = S^T v, the adjoint of bicubic_down. */
+static void bicubic_up(const double* v, int nxs, int nys, int f, double* x) {
+    const int nx = nxs * f, ny = nys * f;
+    double* Sx = (double*)malloc((size_t)nxs * nx * sizeof(double));
+    double* Sy = (double*)malloc((size_t)nys * ny * sizeof(double));
+    double* t = (double*)calloc((size_t)nys * nx, sizeof(double));
+    orc_bicubic_matrix(nx, f, Sx);
+    orc_bicubic_matrix(ny, f, Sy);
+    for (int R = 0; R < nys; ++R)
+        for (int C = 0; C < nxs; ++C)
+            for (int c = 0; c < nx; ++c) t[(size_t)R * nx + c] += Sx[(size_t)C * nx + c] * v[(size_t)R * nxs + C];
+    for (int r = 0; r < ny; ++r)
+        for (int c = 0; c < nx; ++c) {
+            double acc = 0.0;
+            for (int R = 0; R < nys; ++R) acc += Sy[(size_t)R * ny + r] * t[(size_t)R * nx + c];
+            x[(size_t)r * nx + c] = acc;
+        }
+    free(Sx);
+    free(Sy);
+    free(t);
+}
+
+/* The sketch S of kind 0 (f x f average pooling D) or 1 (bicubic), and U = S^T. */
+void orc_sketch_down(int kind, const double* x, int nx, int ny, int f, double* v) {
+    if (kind == 1) bicubic_down(x, nx, ny, f, v);
+    else orc_down(x, nx, ny, f, v);
+}
+
+void orc_sketch_up(int kind, const double* v, int nxs, int nys, int f, double* x) {
+    if (kind == 1) bicubic_up(v, nxs, nys, f, x);
+    else orc_up(v, nxs, nys, f, x);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Sketched (minibatch) gradient, Sec. 2.1, Eqs. (6)-(7)                      */
 /* ------------------------------------------------------------------------- */
 
@@ -292,24 +392,29 @@ void orc_up(const double* v, int nxs, int nys, int f, double* x) {
  * b is the full sinogram (n_views x n_bins); M keeps the rows of `views`.
  * y and g are full-resolution (ny x nx).
  */
-void orc_grad(const orc_geom* g, int f, const double* y, const double* b, const int32_t* views,
-              int n_sel, double sigma, double* grad) {
+void orc_grad_k(const orc_geom* g, int kind, int f, const double* y, const double* b, const int32_t* views,
+                int n_sel, double sigma, double* grad) {
     int nx = g->nx, ny = g->ny, nxs = nx / f, nys = ny / f, nb = g->n_bins;
     size_t ds = (size_t)nxs * nys, ns = (size_t)n_sel * nb;
     double* v = (double*)malloc(ds * sizeof(double));
     double* r = (double*)malloc(ns * sizeof(double));
     double* gs = (double*)malloc(ds * sizeof(double));
-    orc_down(y, nx, ny, f, v);
+    orc_sketch_down(kind, y, nx, ny, f, v);
     orc_fp(g, f, v, r, views, n_sel);
     for (int i = 0; i < n_sel; ++i) {
         int k = view_of(views, i);
         for (int j = 0; j < nb; ++j) r[(size_t)i * nb + j] -= b[(size_t)k * nb + j];
     }
     orc_bp(g, f, r, gs, views, n_sel, sigma);
-    orc_up(gs, nxs, nys, f, grad);
+    orc_sketch_up(kind, gs, nxs, nys, f, grad);
     free(v);
     free(r);
     free(gs);
+}
+
+void orc_grad(const orc_geom* g, int f, const double* y, const double* b, const int32_t* views, int n_sel,
+              double sigma, double* grad) {
+    orc_grad_k(g, 0, f, y, b, views, n_sel, sigma, grad);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -384,10 +489,10 @@ void orc_tv_prox(const double* z, int nx, int ny, double lambda, int n_iter, dou
  *   y_t = x_t + a_t (x_t - x_{t-1}).
  * history (optional): T x (ny*nx) iterates x_t. x_out: x_T.
  */
-void orc_pnp_run(const orc_geom* g, int T, const int32_t* factor, const int32_t* views,
-                 const int32_t* view_off, const int32_t* n_sel, const double* sigma,
-                 const double* eta, const double* a, double alpha, double lambda, int tv_iters,
-                 double tau, const double* b, const double* x0, double* x_out, double* history) {
+void orc_pnp_run_k(const orc_geom* g, int kind, int T, const int32_t* factor, const int32_t* views,
+                   const int32_t* view_off, const int32_t* n_sel, const double* sigma, const double* eta,
+                   const double* a, double alpha, double lambda, int tv_iters, double tau, const double* b,
+                   const double* x0, double* x_out, double* history) {
     size_t n = (size_t)g->nx * g->ny;
     double* x_prev = (double*)malloc(n * sizeof(double));
     double* y = (double*)malloc(n * sizeof(double));
@@ -399,7 +504,7 @@ void orc_pnp_run(const orc_geom* g, int T, const int32_t* factor, const int32_t*
     for (int t = 0; t < T; ++t) {
         const int32_t* vw = views ? views + view_off[t] : NULL;
         int ns = views ? n_sel[t] : g->n_views;
-        orc_grad(g, factor[t], y, b, vw, ns, sigma[t], gr);
+        orc_grad_k(g, kind, factor[t], y, b, vw, ns, sigma[t], gr);
         for (size_t i = 0; i < n; ++i) z[i] = y[i] - eta[t] * gr[i];
         orc_tv_prox(z, g->nx, g->ny, lambda, tv_iters, tau, x);
         for (size_t i = 0; i < n; ++i) x[i] = (1.0 - alpha) * z[i] + alpha * x[i];
@@ -413,6 +518,14 @@ void orc_pnp_run(const orc_geom* g, int T, const int32_t* factor, const int32_t*
     free(z);
     free(x);
     free(gr);
+}
+
+void orc_pnp_run(const orc_geom* g, int T, const int32_t* factor, const int32_t* views, const int32_t* view_off,
+                 const int32_t* n_sel, const double* sigma, const double* eta, const double* a, double alpha,
+                 double lambda, int tv_iters, double tau, const double* b, const double* x0, double* x_out,
+                 double* history) {
+    orc_pnp_run_k(g, 0, T, factor, views, view_off, n_sel, sigma, eta, a, alpha, lambda, tv_iters, tau, b, x0,
+                  x_out, history);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -492,7 +605,7 @@ void orc_pnp_run_vr(const orc_geom* g, int T, const int32_t* factor, const int32
  * Power iteration on B^T B with B = A_s D_f over all views, from v = 1/sqrt(d):
  * v <- B^T B v / ||B^T B v||, n_iter times; returns ||B v||^2.
  */
-double orc_power_lipschitz(const orc_geom* g, int f, int n_iter) {
+double orc_power_lipschitz_k(const orc_geom* g, int kind, int f, int n_iter) {
     int nx = g->nx, ny = g->ny, nxs = nx / f, nys = ny / f;
     size_t d = (size_t)nx * ny, ds = (size_t)nxs * nys, ns = (size_t)g->n_views * g->n_bins;
     double* v = (double*)malloc(d * sizeof(double));
@@ -502,16 +615,16 @@ double orc_power_lipschitz(const orc_geom* g, int f, int n_iter) {
     double* s = (double*)malloc(ns * sizeof(double));
     for (size_t i = 0; i < d; ++i) v[i] = 1.0 / sqrt((double)d);
     for (int it = 0; it < n_iter; ++it) {
-        orc_down(v, nx, ny, f, vs);
+        orc_sketch_down(kind, v, nx, ny, f, vs);
         orc_fp(g, f, vs, s, NULL, g->n_views);
         orc_bp(g, f, s, ws, NULL, g->n_views, 1.0);
-        orc_up(ws, nxs, nys, f, w);
+        orc_sketch_up(kind, ws, nxs, nys, f, w);
         double nrm = 0.0;
         for (size_t i = 0; i < d; ++i) nrm += w[i] * w[i];
         nrm = sqrt(nrm);
         for (size_t i = 0; i < d; ++i) v[i] = w[i] / nrm;
     }
-    orc_down(v, nx, ny, f, vs);
+    orc_sketch_down(kind, v, nx, ny, f, vs);
     orc_fp(g, f, vs, s, NULL, g->n_views);
     double L = 0.0;
     for (size_t i = 0; i < ns; ++i) L += s[i] * s[i];
@@ -522,6 +635,8 @@ double orc_power_lipschitz(const orc_geom* g, int f, int n_iter) {
     free(s);
     return L;
 }
+
+double orc_power_lipschitz(const orc_geom* g, int f, int n_iter) { return orc_power_lipschitz_k(g, 0, f, n_iter); }
 
 /* Peak signal-to-noise ratio with peak = max(ref) - min(ref), MSE over all pixels. */
 double orc_psnr(const double* x, const double* ref, size_t n) {
