@@ -796,8 +796,9 @@ def psnr_vs_time(torch, fbpnp, plan, stage_of, b, xt, blocks, eta, alpha, lam, t
 def paper_scenarios(torch, fbpnp, synth, tune_cache):
     """The paper's experiments (Sec. 3) on synthetic disk phantoms: sparse-view, low-dose
     and limited-angle fan-beam CT at 256^2 with 228 bins and Poisson transmission data;
-    PnP-MS2G Option 1 with the two-stage sketch (25 iterations at f = 4, 75 at f = 2)
-    against PnP-FISTA (100 full-gradient iterations), same TV-prox denoiser, eta = 1/L per
+    PnP-MS2G Option 1 with the two-stage sketch (25 iterations at f = 4, 75 at f = 2;
+    average pooling and, as in the paper, bicubic resizing) against PnP-FISTA (100
+    full-gradient iterations), same TV-prox denoiser, eta = 1/L per
     stage, FISTA momentum. Reports each method's PSNR curve, and the GPU time and the
     projector work (Joseph samples of forward and back-projection) each needs to come
     within 0.1 / 0.5 / 1 dB of PnP-FISTA's final PSNR."""
@@ -818,6 +819,11 @@ def paper_scenarios(torch, fbpnp, synth, tune_cache):
         kw = dict(alpha=sc.alpha, lam=sc.lam, tau=sc.tau, tv_iters=sc.tv_iters)
         ps_sk, t_sk = psnr_vs_time(torch, fbpnp, plan, stage_of, b, xt, list(sc.stages), eta, **kw)
         ps_fu, t_fu = psnr_vs_time(torch, fbpnp, plan, stage_of, b, xt, [(1, sc.full_iters)], eta, **kw)
+        # the paper's own sketch operator: bicubic S with U = S^T (its own step sizes 1/L)
+        plan.set_sketch("bicubic")
+        eta_b = {f: 1.0 / fbpnp.power_lipschitz(plan, stage_of[f], 100) for f in factors}
+        ps_bi, t_bi = psnr_vs_time(torch, fbpnp, plan, stage_of, b, xt, list(sc.stages), eta_b, **kw)
+        plan.set_sketch("pool")
         p_ref = float(ps_fu[-1])
 
         def first(ps, ts, target):
@@ -830,7 +836,8 @@ def paper_scenarios(torch, fbpnp, synth, tune_cache):
         w_fu = np.cumsum([work[1]] * sc.full_iters)
         res = {"views": V, "bins": B, "angle_range_deg": round(float(np.degrees(sc.angle_range)), 1), "i0": sc.i0,
                "pnp_fista_final_psnr_db": round(p_ref, 3)}
-        for key, ps, ts, ws in (("ms2g_two_stage", ps_sk, t_sk, w_sk), ("pnp_fista", ps_fu, t_fu, w_fu)):
+        for key, ps, ts, ws in (("ms2g_two_stage", ps_sk, t_sk, w_sk), ("ms2g_two_stage_bicubic", ps_bi, t_bi, w_sk),
+                                ("pnp_fista", ps_fu, t_fu, w_fu)):
             res[key] = {"iterations": int(len(ps)), "final_psnr_db": round(float(ps[-1]), 3),
                         "max_psnr_db": round(float(ps.max()), 3), "total_ms": round(float(ts[-1]), 4),
                         **{f"ms_to_ref_minus_{d}": first(ps, ts, p_ref - d) for d in (0.1, 0.5, 1.0)},
@@ -838,9 +845,10 @@ def paper_scenarios(torch, fbpnp, synth, tune_cache):
                         "psnr_curve_every_10": [round(float(v), 2) for v in ps[9::10]]}
         for d in (0.1, 0.5, 1.0):
             for unit, tag in (("ms", "speedup"), ("gsamples", "work_ratio")):
-                a_ = res["ms2g_two_stage"][f"{unit}_to_ref_minus_{d}"]
-                b_ = res["pnp_fista"][f"{unit}_to_ref_minus_{d}"]
-                res[f"{tag}_to_ref_minus_{d}"] = None if (a_ is None or b_ is None) else round(b_ / a_, 3)
+                for key, suffix in (("ms2g_two_stage", ""), ("ms2g_two_stage_bicubic", "_bicubic")):
+                    a_ = res[key][f"{unit}_to_ref_minus_{d}"]
+                    b_ = res["pnp_fista"][f"{unit}_to_ref_minus_{d}"]
+                    res[f"{tag}{suffix}_to_ref_minus_{d}"] = None if (a_ is None or b_ is None) else round(b_ / a_, 3)
         out[name] = res
         log(f"scenario {name}: {res}")
         plan.close()

@@ -96,6 +96,25 @@ fb_status fb_plan_stage_info(const fb_plan* plan, int stage, fb_stage_info* out)
 fb_status fb_plan_view_samples(const fb_plan* plan, int stage, int64_t* out);
 
 /*
+ * Sketch operator of the plan's stages with f > 1 (Sec. 2.1, Eqs. (4), (6)):
+ *   kind 0  f x f average pooling D, U = D^T (default);
+ *   kind 1  bicubic resizing (Sec. 3): Keys' cubic convolution kernel, a = -1/2,
+ *           stretched by f against aliasing, output o of each axis centred at
+ *           input coordinate (o + 1/2) f - 1/2, taps beyond the ends folded
+ *           back by half-sample reflection, rows normalised to 1; separable;
+ *           U = S^T (so the sketched gradient stays exact).
+ * fb_plan_set_sketch allocates the bicubic tables (a set-up call, not under
+ * capture). With kind 1, pnp_step sketches y anew at such stages (the
+ * pooling hand-over of fb_graph_create is skipped for them), vr_mode must be
+ * 0 and pnp_step_vjp is unavailable there; fb_power_lipschitz uses the kind.
+ * fb_plan_sketch_down / fb_plan_sketch_up apply the stage's S (x: device
+ * [ny][nx] -> v: [nys][nxs]) and U = S^T (v -> x).
+ */
+fb_status fb_plan_set_sketch(fb_plan* plan, int kind);
+fb_status fb_plan_sketch_down(const fb_plan* plan, int stage, const float* x, float* v, hipStream_t stream);
+fb_status fb_plan_sketch_up(const fb_plan* plan, int stage, const float* v, float* x, hipStream_t stream);
+
+/*
  * Launch configuration of a stage's kernels (no effect on what is computed,
  * only on how the work is split; results can differ in the last bits where
  * the split changes a summation order):

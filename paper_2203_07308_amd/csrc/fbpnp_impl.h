@@ -51,6 +51,20 @@ struct Stage {
 
 }  // namespace fbpnp
 
+namespace fbpnp {
+// One axis of a bicubic sketch table on the device: output r reads inputs
+// lo[r] .. lo[r] + taps - 1 with weights w[r * taps + t].
+struct SketchAxis {
+    int* lo = nullptr;
+    float* w = nullptr;
+    int taps = 0;
+};
+// S along x (nxs outputs) and y (nys outputs), and S^T along x (nx) and y (ny).
+struct StageSketch {
+    SketchAxis dx, dy, ux, uy;
+};
+}  // namespace fbpnp
+
 struct fb_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -68,6 +82,11 @@ struct fb_plan {
     float* vec = nullptr;      // power iteration: 2 x [ny][nx] + reductions
     size_t vec_floats = 0;
     std::vector<fb_launch_config> cfg;  // per stage; zero fields: defaults
+    // sketch of the stages with f > 1: 0 average pooling, 1 bicubic (tables below)
+    int sketch = 0;
+    std::vector<fbpnp::StageSketch> sk;
+    float* sk_tmp = nullptr;  // [ny][nx / f] of the largest coarse width
+    float* sk_g = nullptr;    // coarse gradient [nys][nxs]
 };
 
 namespace fbpnp {
@@ -80,6 +99,9 @@ fb_status hip_fail(hipError_t e, const char* what);
 fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays, std::vector<ViewRec>& views,
                              std::vector<int64_t>& view_samples);
 fb_status validate_geometry(const fb_geom& g);
+// Bicubic sketch table of one axis (n pixels, factor f): S (n / f rows) or its
+// adjoint S^T (n rows), each row a window of `taps` consecutive inputs.
+fb_status bicubic_axis_tables(int n, int f, bool adjoint, std::vector<int>& lo, std::vector<float>& w, int& taps);
 
 // ---- launch helpers (kernels.hip), used by the forward and reverse entry points
 constexpr int kRedBlocks = 256;  // blocks of the two-pass reductions
@@ -135,6 +157,15 @@ fb_status launch_tv_single(const float* z, int nx, int ny, float lam, float tau,
                            float* p_out, int mode, float alpha, float a_t, const float* x_prev, float* x_out,
                            float* y_out, float* hist, hipStream_t s, const PoolTarget& pt = PoolTarget(),
                            int tile = 0);
+
+// Bicubic sketch (plans with sketch == 1, stages with f > 1): S of x into the
+// stage's line images (or into v when v is set), and out = yprev - scale S^T g
+// (out = scale S^T g when yprev is NULL).
+fb_status launch_bicubic_down(const fb_plan* p, int stage, const float* x, float* v, hipStream_t s);
+fb_status launch_bicubic_up(const fb_plan* p, int stage, const float* g, float scale, const float* yprev, float* out,
+                            hipStream_t s);
+inline bool bicubic_stage(const fb_plan* p, int stage) { return p->sketch == 1 && p->stages[stage].f > 1; }
+void release_sketch(fb_plan* p);  // frees the bicubic tables (back to pooling)
 
 // Captures what body launches on a private stream into an instantiated graph.
 fb_status capture_graph(const std::function<fb_status(hipStream_t)>& body, fb_graph** out);

@@ -432,6 +432,7 @@ fb_status fb_plan_destroy(fb_plan* p) {
     if (p->resid) (void)hipFree(p->resid);
     if (p->zbuf) (void)hipFree(p->zbuf);
     if (p->vec) (void)hipFree(p->vec);
+    release_sketch(p);
     delete p;
     return FB_OK;
 }
@@ -546,6 +547,52 @@ fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_
                             stream);
 }
 
+// The TV epilogue's hand-over of y_t to the next step's stage: its pooling
+// into that stage's line images (not for bicubic stages, which sketch anew).
+static PoolTarget pool_target(const fb_plan* p, int next_stage) {
+    PoolTarget pt;
+    if (next_stage < 0 || bicubic_stage(p, next_stage)) return pt;
+    const Stage& N = p->stages[next_stage];
+    StageLines L = stage_lines(p, next_stage);
+    pt.f = N.f;
+    pt.inv = 1.f / (float)(N.f * N.f);
+    pt.lx = L.lx;
+    pt.ly = L.ly;
+    pt.px = N.pitch_x;
+    pt.py = N.pitch_y;
+    pt.nxs = N.nxs;
+    pt.nys = N.nys;
+    return pt;
+}
+
+// pnp_step at a stage with the bicubic sketch: S into the line images, the
+// residual projection, the back-projection into the coarse gradient g, then
+// z = y_{t-1} - eta sigma S^T g and the denoiser.
+static fb_status pnp_step_bicubic(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
+    fb_status st;
+    if (a->vr_mode != 0) return fail(FB_EINVAL, "pnp_step: variance reduction is defined with the pooling sketch");
+    const int nx = p->g.nx, ny = p->g.ny;
+    if ((st = launch_bicubic_down(p, a->stage, a->y_prev, nullptr, stream)) != FB_OK) return st;
+    {
+        TimedLaunch tl(a->events, 0);
+        if ((st = launch_fp(p, a->stage, true, a->views, a->n_sel, a->b, p->resid, stream)) != FB_OK) return st;
+    }
+    {
+        TimedLaunch tl(a->events, 2);
+        if ((st = launch_bp_t<false>(p, a->stage, p->resid, a->views, a->n_sel, 1.f, p->sk_g, nullptr, nullptr,
+                                     stream)) != FB_OK)
+            return st;
+    }
+    if ((st = launch_bicubic_up(p, a->stage, p->sk_g, a->eta * a->sigma, a->y_prev, p->zbuf, stream)) != FB_OK)
+        return st;
+    const float lam = a->lambda > 0.f ? a->lambda : 1.f;
+    const int iters = a->lambda > 0.f ? a->tv_iters : 0;
+    TimedLaunch tl(a->events, 4);
+    return launch_tv_single(p->zbuf, nx, ny, lam, a->tau, iters, nullptr, nullptr, 1, a->alpha, a->a_t, a->x_prev,
+                            a->x_out, a->y_out, a->history, stream, pool_target(p, a->next_stage),
+                            plan_config(p, a->stage, a->n_sel).tv_tile);
+}
+
 fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
     if (!a) return fail(FB_EINVAL, "pnp_step: args is NULL");
     fb_status st = check_stage(p, a->stage);
@@ -565,6 +612,7 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
         return fail(FB_ESUBSET, "pnp_step: a snapshot step uses every view");
     const Stage& S = p->stages[a->stage];
     const int nx = p->g.nx, ny = p->g.ny;
+    if (bicubic_stage(p, a->stage)) return pnp_step_bicubic(p, a, stream);
     if (!a->prepared && (st = launch_prepare(p, a->stage, a->y_prev, nx, S.f, stream)) != FB_OK) return st;
     // variance-reduced modes: 1 records the snapshot's projection and coarse
     // gradient; 2 projects against the snapshot's projection and adds its gradient
@@ -583,19 +631,7 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
                                     snap ? a->snap_grad : nullptr)) != FB_OK)
             return st;
     }
-    PoolTarget pt;
-    if (a->next_stage >= 0) {
-        const Stage& N = p->stages[a->next_stage];
-        StageLines L = stage_lines(p, a->next_stage);
-        pt.f = N.f;
-        pt.inv = 1.f / (float)(N.f * N.f);
-        pt.lx = L.lx;
-        pt.ly = L.ly;
-        pt.px = N.pitch_x;
-        pt.py = N.pitch_y;
-        pt.nxs = N.nxs;
-        pt.nys = N.nys;
-    }
+    const PoolTarget pt = pool_target(p, a->next_stage);
     // lambda == 0 or no TV iterations: D is the identity, the same kernel then
     // only applies the relaxation and momentum (div p = 0)
     const float lam = a->lambda > 0.f ? a->lambda : 1.f;
@@ -662,13 +698,19 @@ fb_status fb_power_lipschitz(const fb_plan* p, int stage, int n_iter, double* ou
     const int fill_blocks = std::min<size_t>(1024, (npix + 255) / 256);
     k_fill<<<fill_blocks, 256, 0, stream>>>(v, npix, (float)(1.0 / std::sqrt((double)npix)));
     if ((st = check_launch("power: fill")) != FB_OK) return st;
+    const bool bic = bicubic_stage(p, stage);
     for (int it = 0; it <= n_iter; ++it) {
-        if ((st = launch_prepare(p, stage, v, nx, S.f, stream)) != FB_OK) return st;
+        st = bic ? launch_bicubic_down(p, stage, v, nullptr, stream) : launch_prepare(p, stage, v, nx, S.f, stream);
+        if (st != FB_OK) return st;
         if ((st = launch_fp(p, stage, false, nullptr, nv, nullptr, p->resid, stream)) != FB_OK) return st;
         if (it == n_iter) break;
         if ((st = launch_bp_t<false>(p, stage, p->resid, nullptr, nv, 1.f, gs, nullptr, nullptr, stream)) != FB_OK)
             return st;
-        k_up<<<dim3(cdiv(nx, 256), ny), 256, 0, stream>>>(gs, S.nxs, S.f, inv_ff, nx, ny, w);
+        if (bic) {
+            if ((st = launch_bicubic_up(p, stage, gs, 1.f, nullptr, w, stream)) != FB_OK) return st;
+        } else {
+            k_up<<<dim3(cdiv(nx, 256), ny), 256, 0, stream>>>(gs, S.nxs, S.f, inv_ff, nx, ny, w);
+        }
         k_sumsq_partial<<<kRedBlocks, 256, 0, stream>>>(w, npix, part);
         k_sum_final<<<1, 256, 0, stream>>>(part, kRedBlocks, sum);
         k_normalise<<<fill_blocks, 256, 0, stream>>>(w, v, npix, sum);

@@ -5,6 +5,7 @@
 // one Joseph ray per bin centre, pixel centres at ((c-(nx-1)/2) h, (r-(ny-1)/2) h).
 // Stage grids (pooling factor f, Sec. 2.1 Eq. (4)) keep the same isocentre and
 // use pixel f h.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -180,6 +181,66 @@ fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays,
         v.xhi = xhi;
         v.ylo = ylo;
         v.yhi = yhi;
+    }
+    return FB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Bicubic sketch tables (Sec. 3: resizing with bicubic interpolation).
+// Output o of an axis of n pixels reduced by f sits at input coordinate
+// (o + 1/2) f - 1/2; its weights are Keys' cubic convolution kernel (a = -1/2)
+// at (i - u) / f, the taps outside the axis folded back by half-sample
+// reflection, normalised to sum 1. The adjoint table lists, for each input i,
+// the outputs whose weights reach it.
+// ---------------------------------------------------------------------------
+static double keys_cubic(double s) {
+    const double a = -0.5, t = std::fabs(s);
+    if (t <= 1.0) return ((a + 2.0) * t - (a + 3.0)) * t * t + 1.0;
+    if (t < 2.0) return ((a * t - 5.0 * a) * t + 8.0 * a) * t - 4.0 * a;
+    return 0.0;
+}
+
+static int fold_index(int i, int n) {
+    while (i < 0 || i >= n) i = i < 0 ? -1 - i : 2 * n - 1 - i;
+    return i;
+}
+
+fb_status bicubic_axis_tables(int n, int f, bool adjoint, std::vector<int>& lo, std::vector<float>& w, int& taps) {
+    if (n < 1 || f < 1 || n % f) return fail(FB_EDIV, "bicubic sketch: size not divisible by f");
+    const int m = n / f;
+    std::vector<double> S((size_t)m * n, 0.0);
+    for (int o = 0; o < m; ++o) {
+        const double u = (o + 0.5) * f - 0.5;
+        double sum = 0.0;
+        for (int i = (int)std::floor(u - 2.0 * f); i <= (int)std::ceil(u + 2.0 * f); ++i) {
+            const double k = keys_cubic((i - u) / f);
+            if (k == 0.0) continue;
+            S[(size_t)o * n + fold_index(i, n)] += k;
+            sum += k;
+        }
+        for (int i = 0; i < n; ++i) S[(size_t)o * n + i] /= sum;
+    }
+    const int rows = adjoint ? n : m, cols = adjoint ? m : n;
+    auto at = [&](int r, int c) { return adjoint ? S[(size_t)c * n + r] : S[(size_t)r * n + c]; };
+    std::vector<int> first(rows, cols), last(rows, -1);
+    taps = 1;
+    for (int r = 0; r < rows; ++r) {
+        for (int c = 0; c < cols; ++c)
+            if (at(r, c) != 0.0) {
+                first[r] = std::min(first[r], c);
+                last[r] = c;
+            }
+        if (last[r] >= first[r]) taps = std::max(taps, last[r] - first[r] + 1);
+    }
+    taps = std::min(taps, cols);
+    lo.assign(rows, 0);
+    w.assign((size_t)rows * taps, 0.f);
+    for (int r = 0; r < rows; ++r) {
+        // a window of `taps` inputs inside the axis that holds every nonzero weight
+        const int l = std::max(0, std::min(last[r] >= first[r] ? first[r] : 0, cols - taps));
+        if (last[r] >= l + taps) return fail(FB_EINVAL, "bicubic sketch: weight window");
+        lo[r] = l;
+        for (int t = 0; t < taps; ++t) w[(size_t)r * taps + t] = (float)at(r, l + t);
     }
     return FB_OK;
 }

@@ -243,6 +243,7 @@ fb_status pnp_step_vjp(const fb_plan* p, const fb_pnp_args* a, const float* xbar
     if ((st = check_views(p, a->views, a->n_sel)) != FB_OK) return st;
     if (!a->b || !a->y_prev) return fail(FB_EINVAL, "pnp_step_vjp: null buffer in args");
     if (a->vr_mode != 0) return fail(FB_EINVAL, "pnp_step_vjp: variance-reduced steps are not differentiated");
+    if (bicubic_stage(p, a->stage)) return fail(FB_EINVAL, "pnp_step_vjp: differentiated with the pooling sketch only");
     if (a->tv_iters < 0 || a->tv_iters > 64) return fail(FB_EINVAL, "pnp_step_vjp: tv_iters out of range");
     if (!(a->lambda >= 0.f) || !(a->tau > 0.f)) return fail(FB_EINVAL, "pnp_step_vjp: need lambda >= 0 and tau > 0");
     if (!ws || ws_bytes < fb_pnp_vjp_workspace_bytes(p, a->tv_iters))

@@ -27,7 +27,8 @@ EXPORTS = [
     "fb_pnp_vjp_workspace_bytes", "pnp_step_vjp", "fb_power_lipschitz", "fb_plan_view_samples",
     "fb_plan_set_config", "fb_plan_get_config", "fb_batch_create", "fb_batch_destroy", "fb_batch_layout",
     "fb_batch_slice_plan", "fb_batch_set_config", "fb_batch_get_config", "pnp_step_batched",
-    "fb_batch_graph_create", "fb_autotune", "fb_batch_autotune",
+    "fb_batch_graph_create", "fb_autotune", "fb_batch_autotune", "fb_plan_set_sketch", "fb_plan_sketch_down",
+    "fb_plan_sketch_up",
 ]
 
 
@@ -116,6 +117,9 @@ def load() -> ctypes.CDLL:
     lib.fb_graph_destroy.argtypes = [vp]
     lib.fb_plan_view_samples.argtypes = [vp, c_int, P(ctypes.c_int64)]
     lib.fb_plan_set_config.argtypes = [vp, c_int, P(LaunchConfig)]
+    lib.fb_plan_set_sketch.argtypes = [vp, c_int]
+    lib.fb_plan_sketch_down.argtypes = [vp, c_int, vp, vp, vp]
+    lib.fb_plan_sketch_up.argtypes = [vp, c_int, vp, vp, vp]
     lib.fb_plan_get_config.argtypes = [vp, c_int, c_int, P(LaunchConfig)]
     lib.fb_batch_create.argtypes = [P(Geom), c_int, c_int, P(ctypes.c_int32), P(vp)]
     lib.fb_batch_destroy.argtypes = [vp]
@@ -215,6 +219,25 @@ class Plan:
         """Launch configuration of a stage (fb_launch_config fields; None or 0: defaults)."""
         c = None if cfg is None else ctypes.byref(LaunchConfig(**cfg))
         _check(load().fb_plan_set_config(self._h, stage, c))
+
+    SKETCHES = {"pool": 0, "bicubic": 1}
+
+    def set_sketch(self, kind: str = "pool") -> None:
+        """Sketch of the stages with f > 1: "pool" (f x f average, U = D^T) or "bicubic"
+        (Keys' kernel stretched by f, U = S^T); see fb_plan_set_sketch."""
+        _check(load().fb_plan_set_sketch(self._h, self.SKETCHES[kind]))
+
+    def sketch_down(self, stage: int, x: torch.Tensor, v: torch.Tensor, stream=None) -> torch.Tensor:
+        nys, nxs = self.coarse_shape(stage)
+        _check(load().fb_plan_sketch_down(self._h, stage, _ptr(x, numel=self.geom.nx * self.geom.ny, name="x"),
+                                          _ptr(v, numel=nxs * nys, name="v"), _stream(stream)))
+        return v
+
+    def sketch_up(self, stage: int, v: torch.Tensor, x: torch.Tensor, stream=None) -> torch.Tensor:
+        nys, nxs = self.coarse_shape(stage)
+        _check(load().fb_plan_sketch_up(self._h, stage, _ptr(v, numel=nxs * nys, name="v"),
+                                        _ptr(x, numel=self.geom.nx * self.geom.ny, name="x"), _stream(stream)))
+        return x
 
     def get_config(self, stage: int, n_sel: int | None = None) -> dict:
         out = LaunchConfig()
