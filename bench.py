@@ -162,11 +162,13 @@ def _csv(directory: str, suffix: str):
         return list(csv.DictReader(fh))
 
 
-def label_dispatches(names):
+def label_dispatches(names, grids=None):
     """(group, index) labels of the dispatches that belong to complete replays of the
     sketched schedule, e.g. ("bp_f1", i): a replay is the pooling kernel followed by
     exactly one forward projection, back-projection and denoiser launch per iteration
-    (other sequences, such as the autotuner's timing runs, are skipped)."""
+    (other sequences, such as the autotuner's timing runs, are skipped). With grids
+    (each dispatch's grid size), the denoiser launches of a replay must all have the
+    grid of the 512^2 image, which excludes runs on other image sizes."""
     from paper_2203_07308_amd import synth
 
     w = synth.WORKLOADS["ms2g512"]
@@ -187,9 +189,11 @@ def label_dispatches(names):
                 lab.append((f"{c}_f{stage_f[t]}", j + k))
             j += 3
         else:
-            out += lab
-            i = j
-            continue
+            tv_grids = {grids[k] for g, k in lab if g.startswith("tv")} if grids is not None else None
+            if tv_grids is None or tv_grids == {TV_GRID_512}:
+                out += lab
+                i = j
+                continue
         i += 1
     return out
 
@@ -199,6 +203,7 @@ def trace_summary(args) -> int:
     trace = _csv(args.trace_summary, "kernel_trace.csv")
     trace.sort(key=lambda r: int(r["Start_Timestamp"]))
     names = [_short(r["Kernel_Name"]) for r in trace]
+    grids = [int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) for r in trace]
     out = ["# rocprofv3 kernel trace: 512x512 multi-stage sketched PnP-SGD (720 views x 768 bins, f = 4, 2, 1, "
            "1 of 8 view subsets)", "", "Command (repository root, one MI355X, library built):", "", "```",
            args.cmd, "```", "", "Summary: `python bench.py --trace-summary <output dir> --cmd '<command>'"
@@ -210,7 +215,7 @@ def trace_summary(args) -> int:
                    f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                    f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
     groups = {}
-    for g, j in label_dispatches(names):
+    for g, j in label_dispatches(names, grids):
         groups.setdefault(g, []).append(j)
     n_rep = len(groups.get("tv_f1", [])) // 20 if groups else 0
     out += ["", f"## Per iteration group, over {n_rep} complete replays of the schedule (graph and direct calls)", "",
@@ -243,13 +248,14 @@ def pmc_summary(args) -> int:
         rows = [r for r in rows if r["Counter_Name"] == cname]
         rows.sort(key=lambda r: int(r["Dispatch_Id"]))
         names = [_short(r["Kernel_Name"]) for r in rows]
+        grids = [int(r["Grid_Size"]) for r in rows]
         copies = [r for r, n in zip(rows, names) if n == "__amd_rocclr_copyBuffer"]
         if not copies:
             raise SystemExit("no copy kernel for the calibration")
         copy_kib = float(copies[-1]["Counter_Value"])  # the 64 MiB device copy at the end of --profile
         factor = 65536.0 / copy_kib
         per[cname] = {"copy_kib": copy_kib, "factor": factor, "groups": {}}
-        for g, j in label_dispatches(names):
+        for g, j in label_dispatches(names, grids):
             per[cname]["groups"].setdefault(g, []).append((names[j], float(rows[j]["Counter_Value"])))
     cf, cw = per["FETCH_SIZE"]["factor"], per["WRITE_SIZE"]["factor"]
     out += ["Calibration: a 64 MiB device-to-device copy (`__amd_rocclr_copyBuffer`) reads FETCH_SIZE = "
@@ -274,6 +280,9 @@ def pmc_summary(args) -> int:
     return 0
 
 
+TV_GRID_512 = 512 * 512  # work-items of a denoiser launch on the 512^2 image (one per pixel)
+
+
 # MI355X: 256 CUs x 4 SIMDs; a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
 N_SIMD, VALU_CYCLES, CLOCK_GHZ = 1024, 4, 2.4
 
@@ -291,14 +300,15 @@ def counter_tables(args):
         for cname, rs in by_counter.items():
             rs.sort(key=lambda r: int(r["Dispatch_Id"]))
             names = [_short(r["Kernel_Name"]) for r in rs]
-            for g, j in label_dispatches(names):
+            for g, j in label_dispatches(names, [int(r["Grid_Size"]) for r in rs]):
                 per.setdefault(g, {}).setdefault(cname, []).append(float(rs[j]["Counter_Value"]))
     dur = {}
     if args.trace_dir:
         trace = _csv(args.trace_dir, "kernel_trace.csv")
         trace.sort(key=lambda r: int(r["Start_Timestamp"]))
         names = [_short(r["Kernel_Name"]) for r in trace]
-        for g, j in label_dispatches(names):
+        grids = [int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) for r in trace]
+        for g, j in label_dispatches(names, grids):
             dur.setdefault(g, []).append((int(trace[j]["End_Timestamp"]) - int(trace[j]["Start_Timestamp"])) * 1e-3)
     cnames = sorted({c for v in per.values() for c in v})
     out = ["", "## Further counters (average per dispatch)", "",
