@@ -115,10 +115,13 @@ def test_fanbeam_fp_matches_oracle(name, f, sel):
             assert np.all(got[i] == 0)
 
 
+# backprojector launch shapes: the built-in choice and each pixel block size
+BP_FORMS = [dict(), dict(bp_px=1, bp_vg=16), dict(bp_px=2, bp_vg=4), dict(bp_px=4, bp_vg=1)]
+
+
 @pytest.mark.parametrize("name,f,sel", FP_CASES)
 def test_fanbeam_bp_matches_oracle(name, f, sel):
     gd, og, plan, views = setup_case(name, f, sel)
-    say("bp", name, f, sel)
     nys, nxs = gd["ny"] // f, gd["nx"] // f
     n_sel = gd["n_views"] if views is None else len(views)
     dv = None if views is None else dev(views, np.int32)
@@ -126,28 +129,49 @@ def test_fanbeam_bp_matches_oracle(name, f, sel):
     ysin = oracle.fp(og, ellipse_image(nys, nxs, 5), f, views).astype(np.float32)
     yrnd = (np.random.default_rng(7).random((n_sel, gd["n_bins"])) - 0.5).astype(np.float32)
     for y, tol in ((ysin, 1e-5), (yrnd, 2e-5)):
-        x = torch.empty(nys * nxs, device="cuda")
-        fbpnp.fanbeam_bp(plan, 0, dev(y), x, dv, scale=0.75)
-        got = host(x).reshape(nys, nxs)
         ref = oracle.bp(og, y.astype(np.float64), f, views, 0.75)
-        assert rel(got, ref) <= tol, rel(got, ref)
+        for form in BP_FORMS:
+            say("bp", name, f, sel, form)
+            plan.set_config(0, form)
+            x = torch.empty(nys * nxs, device="cuda")
+            fbpnp.fanbeam_bp(plan, 0, dev(y), x, dv, scale=0.75)
+            got = host(x).reshape(nys, nxs)
+            assert rel(got, ref) <= tol, (form, rel(got, ref))
 
 
-@pytest.mark.parametrize("name,f", [("256", 1), ("512", 4), ("ragged", 2)])
+def test_fanbeam_bp_skips_invalid_views():
+    """View indices outside [0, n_views) add nothing and repeats add twice, in every launch shape."""
+    gd, og, plan, _ = setup_case("ragged", 1, None)
+    views = np.array([36, -1, 17, 37, 17, 1 << 20, 2], dtype=np.int32)
+    ok = (views >= 0) & (views < gd["n_views"])
+    y = (np.random.default_rng(3).random((len(views), gd["n_bins"])) + 0.5).astype(np.float32)
+    ref = oracle.bp(og, y[ok].astype(np.float64), 1, views[ok], 1.0)
+    for form in BP_FORMS:
+        say("bp invalid views", form)
+        plan.set_config(0, form)
+        x = torch.empty(gd["nx"] * gd["ny"], device="cuda")
+        fbpnp.fanbeam_bp(plan, 0, dev(y), x, dev(views, np.int32))
+        assert rel(host(x).reshape(ref.shape), ref) <= 1e-5, form
+
+
+@pytest.mark.parametrize("name,f", [("256", 1), ("512", 4), ("ragged", 2), ("512", 1)])
 def test_fp32_adjoint_identity(name, f):
+    """<A x, y> = <x, A^T y> between the GPU projector and the GPU backprojector (each launch shape)."""
     gd, og, plan, _ = setup_case(name, f, None)
-    say("adjoint", name, f)
     nys, nxs = gd["ny"] // f, gd["nx"] // f
     rng = np.random.default_rng(1)
     x = rng.random((nys, nxs)).astype(np.float32)
     y = rng.random((gd["n_views"], gd["n_bins"])).astype(np.float32)
     ax = torch.empty(y.size, device="cuda")
-    aty = torch.empty(x.size, device="cuda")
     fbpnp.fanbeam_fp(plan, 0, dev(x), ax)
-    fbpnp.fanbeam_bp(plan, 0, dev(y), aty)
     lhs = np.vdot(host(ax), y.ravel().astype(np.float64))
-    rhs = np.vdot(x.ravel().astype(np.float64), host(aty))
-    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    for form in BP_FORMS:
+        say("adjoint", name, f, form)
+        plan.set_config(0, form)
+        aty = torch.empty(x.size, device="cuda")
+        fbpnp.fanbeam_bp(plan, 0, dev(y), aty)
+        rhs = np.vdot(x.ravel().astype(np.float64), host(aty))
+        assert abs(lhs - rhs) <= 1e-5 * abs(lhs), form
 
 
 def test_stage_sample_counts_match_oracle():
