@@ -407,7 +407,12 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
 //   p_in/p_out: optional global dual field [2][ny][nx] for multi-launch runs
 //   (p_out set: the launch stores p for its tile instead of producing x).
 // ---------------------------------------------------------------------------
-// Tile (bx, by) of the TV-prox, NT threads.
+// Tile (bx, by) of the TV-prox, NT threads. Each thread owns vertical pairs
+// of cells (rows 2i, 2i+1 of one column of the haloed tile): their dual
+// values p1, p2 and z / lambda stay in registers, and LDS only carries what a
+// neighbour reads (the lower cell's p1, both p2, both u), so a step moves 11
+// LDS words per pair instead of 26. Arithmetic and its order are those of the
+// plain per-cell form.
 template <int T, int H, int NT>
 __device__ __forceinline__ void tv_body(int bx, int by, const float* __restrict__ z, int nx, int ny, float lam,
                                         float tau, int n_iter, const float* __restrict__ p_in,
@@ -417,81 +422,129 @@ __device__ __forceinline__ void tv_body(int bx, int by, const float* __restrict_
                                         float* __restrict__ plx, int ppx, float* __restrict__ ply, int ppy,
                                         int pnxs, int pnys) {
     constexpr int S = T + 2 * H;
-    constexpr int NC = (S * S + NT - 1) / NT;
-    __shared__ float sz[S * S], sp1[S * S], sp2[S * S], su[S * S];
+    static_assert(S % 2 == 0, "pairs of rows need an even tile side");
+    constexpr int NPAIR = (S / 2) * S;
+    constexpr int NP = (NPAIR + NT - 1) / NT;
+    __shared__ float sp1[S * S], sp2[S * S], su[S * S];
     const int R0 = by * T - H, C0 = bx * T - H;
     const size_t plane = (size_t)nx * ny;
-    // per-thread cells, their clamped neighbour indices and gradient masks
-    int ce[NC], cup[NC], cleft[NC], cdown[NC], cright[NC];
-    float m1[NC], m2[NC];
+    const float il = 1.f / lam;
+    // per pair k: column lc, upper row 2 pr; LDS index of the upper cell and
+    // of its clamped neighbours (a missing neighbour reads the cell itself)
+    int e0[NP], eup[NP], eleft[NP], edown[NP], eright[NP];
+    bool live[NP], out0[NP], out1[NP];
+    float p1a[NP], p1b[NP], p2a[NP], p2b[NP], za[NP], zb[NP], zla[NP], zlb[NP];
+    float m1a[NP], m1b[NP], m2a[NP], m2b[NP], xpa[NP], xpb[NP];
+    size_t ga[NP];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        const int e = threadIdx.x + k * NT;
-        const int ee = e < S * S ? e : S * S - 1;
-        const int lr = ee / S, lc = ee - lr * S;
+    for (int k = 0; k < NP; ++k) {
+        const int q = threadIdx.x + k * NT;
+        live[k] = q < NPAIR;
+        const int qq = live[k] ? q : NPAIR - 1;
+        const int pr = qq / S, lc = qq - pr * S;
+        const int lr = 2 * pr;
+        const int e = lr * S + lc;
+        e0[k] = e;
+        // (the tile's first row reads its pair's lower cell: any finite value
+        // there stays outside what the output tile depends on)
+        eup[k] = lr > 0 ? e - S : e + S;
+        eleft[k] = lc > 0 ? e - 1 : e;
+        edown[k] = lr + 2 < S ? e + 2 * S : e + S;
+        eright[k] = lc < S - 1 ? e + 1 : e;
         const int gr = R0 + lr, gc = C0 + lc;
-        const bool in = gr >= 0 && gr < ny && gc >= 0 && gc < nx;
-        ce[k] = e;
-        cup[k] = lr > 0 ? ee - S : ee;
-        cleft[k] = lc > 0 ? ee - 1 : ee;
-        cdown[k] = lr < S - 1 ? ee + S : ee;
-        cright[k] = lc < S - 1 ? ee + 1 : ee;
-        m1[k] = (in && gr < ny - 1) ? 1.f : 0.f;
-        m2[k] = (in && gc < nx - 1) ? 1.f : 0.f;
-        if (e < S * S) {
-            const size_t gi = (size_t)gr * nx + gc;
-            sz[e] = in ? z[gi] : 0.f;
-            sp1[e] = (in && p_in) ? p_in[gi] : 0.f;
-            sp2[e] = (in && p_in) ? p_in[plane + gi] : 0.f;
+        const bool ina = gr >= 0 && gr < ny && gc >= 0 && gc < nx;
+        const bool inb = gr + 1 >= 0 && gr + 1 < ny && gc >= 0 && gc < nx;
+        m1a[k] = (ina && gr < ny - 1) ? 1.f : 0.f;
+        m1b[k] = (inb && gr + 1 < ny - 1) ? 1.f : 0.f;
+        m2a[k] = (ina && gc < nx - 1) ? 1.f : 0.f;
+        m2b[k] = (inb && gc < nx - 1) ? 1.f : 0.f;
+        const size_t gi = (size_t)gr * nx + gc;
+        ga[k] = gi;
+        za[k] = ina ? z[gi] : 0.f;
+        zb[k] = inb ? z[gi + nx] : 0.f;
+        p1a[k] = (ina && p_in) ? p_in[gi] : 0.f;
+        p1b[k] = (inb && p_in) ? p_in[gi + nx] : 0.f;
+        p2a[k] = (ina && p_in) ? p_in[plane + gi] : 0.f;
+        p2b[k] = (inb && p_in) ? p_in[plane + gi + nx] : 0.f;
+        zla[k] = za[k] * il;
+        zlb[k] = zb[k] * il;
+        // output cells of the tile; their x_prev is fetched now, used at the end
+        const bool col_out = lc >= H && lc < H + T && gc < nx;
+        out0[k] = live[k] && col_out && lr >= H && lr < H + T && gr < ny;
+        out1[k] = live[k] && col_out && lr + 1 >= H && lr + 1 < H + T && gr + 1 < ny;
+        xpa[k] = (out0[k] && mode == 1 && !p_out) ? x_prev[gi] : 0.f;
+        xpb[k] = (out1[k] && mode == 1 && !p_out) ? x_prev[gi + nx] : 0.f;
+        if (live[k]) {
+            sp1[e + S] = p1b[k];
+            sp2[e] = p2a[k];
+            sp2[e + S] = p2b[k];
         }
     }
     __syncthreads();
-    const float il = 1.f / lam;
     for (int it = 0; it < n_iter; ++it) {
+        float ua[NP], ub[NP];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int e = ce[k];
-            if (e < S * S) su[e] = (sp1[e] - sp1[cup[k]]) + (sp2[e] - sp2[cleft[k]]) - sz[e] * il;
+        for (int k = 0; k < NP; ++k) {
+            const int e = e0[k];
+            // u = div p - z / lambda on both cells
+            ua[k] = (p1a[k] - sp1[eup[k]]) + (p2a[k] - sp2[eleft[k]]) - zla[k];
+            ub[k] = (p1b[k] - p1a[k]) + (p2b[k] - sp2[eleft[k] + S]) - zlb[k];
+            if (live[k]) {
+                su[e] = ua[k];
+                su[e + S] = ub[k];
+            }
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int e = ce[k];
-            if (e < S * S) {
-                const float u = su[e];
-                const float q1 = m1[k] * (su[cdown[k]] - u);
-                const float q2 = m2[k] * (su[cright[k]] - u);
-                const float inv = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(fmaf(q1, q1, q2 * q2)), 1.f));
-                sp1[e] = fmaf(tau, q1, sp1[e]) * inv;
-                sp2[e] = fmaf(tau, q2, sp2[e]) * inv;
+        for (int k = 0; k < NP; ++k) {
+            const int e = e0[k];
+            const float q1a = m1a[k] * (ub[k] - ua[k]);
+            const float q1b = m1b[k] * (su[edown[k]] - ub[k]);
+            const float q2a = m2a[k] * (su[eright[k]] - ua[k]);
+            const float q2b = m2b[k] * (su[eright[k] + S] - ub[k]);
+            const float ia = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(fmaf(q1a, q1a, q2a * q2a)), 1.f));
+            const float ib = __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(fmaf(q1b, q1b, q2b * q2b)), 1.f));
+            p1a[k] = fmaf(tau, q1a, p1a[k]) * ia;
+            p2a[k] = fmaf(tau, q2a, p2a[k]) * ia;
+            p1b[k] = fmaf(tau, q1b, p1b[k]) * ib;
+            p2b[k] = fmaf(tau, q2b, p2b[k]) * ib;
+            if (live[k]) {
+                sp1[e + S] = p1b[k];
+                sp2[e] = p2a[k];
+                sp2[e + S] = p2b[k];
             }
         }
         __syncthreads();
     }
     float* const yst = su;  // free after the last step: holds y_t for the pooling epilogue
-    for (int e = threadIdx.x; e < T * T; e += NT) {
-        const int tr = e / T, tc = e - tr * T;
-        const int gr = R0 + H + tr, gc = C0 + H + tc;
-        if (gr >= ny || gc >= nx) continue;
-        const int l = (H + tr) * S + (H + tc);
-        const size_t gi = (size_t)gr * nx + gc;
-        if (p_out) {
-            p_out[gi] = sp1[l];
-            p_out[plane + gi] = sp2[l];
-            continue;
-        }
-        const float d = (sp1[l] - sp1[l - S]) + (sp2[l] - sp2[l - 1]);
-        const float zz = sz[l];
-        const float den = fmaf(-lam, d, zz);
-        if (mode == 0) {
-            x_out[gi] = den;
-        } else {
-            const float xr = (1.f - alpha) * zz + alpha * den;
-            const float yn = fmaf(a_t, xr - x_prev[gi], xr);
-            x_out[gi] = xr;
-            y_out[gi] = yn;
-            if (hist) hist[gi] = xr;
-            yst[l] = yn;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e = e0[k];
+        const size_t gi = ga[k];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (!(h == 0 ? out0[k] : out1[k])) continue;
+            const size_t g = h == 0 ? gi : gi + nx;
+            const float p1 = h == 0 ? p1a[k] : p1b[k], p2 = h == 0 ? p2a[k] : p2b[k];
+            if (p_out) {
+                p_out[g] = p1;
+                p_out[plane + g] = p2;
+                continue;
+            }
+            const float p1u = h == 0 ? sp1[eup[k]] : p1a[k];
+            const float d = (p1 - p1u) + (p2 - sp2[eleft[k] + h * S]);
+            const float zz = h == 0 ? za[k] : zb[k];
+            const float den = fmaf(-lam, d, zz);
+            if (mode == 0) {
+                x_out[g] = den;
+            } else {
+                const float xr = (1.f - alpha) * zz + alpha * den;
+                const float yn = fmaf(a_t, xr - (h == 0 ? xpa[k] : xpb[k]), xr);
+                x_out[g] = xr;
+                y_out[g] = yn;
+                if (hist) hist[g] = xr;
+                yst[e + h * S] = yn;
+            }
         }
     }
     if (pf > 0) {
