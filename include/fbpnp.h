@@ -76,8 +76,8 @@ typedef struct fb_plan fb_plan;
 const char* fb_last_error(void);
 
 /*
- * Creates a plan for one geometry and n_stages pooling factors (each >= 1,
- * dividing nx and ny). Stage s is the Joseph projector A_s on the
+ * Creates a plan for one geometry and n_stages pooling factors (each in
+ * 1..32, dividing nx and ny; FB_EINVAL otherwise). Stage s is the Joseph projector A_s on the
  * (ny/f_s) x (nx/f_s) grid with pixel f_s h (Sec. 2.1, Eq. (4)). Ray tables are
  * computed in double precision on the host and stored in float32 on the
  * device. Allocates device memory and synchronises the current device.

@@ -270,6 +270,59 @@ __device__ __forceinline__ void bp_class(const ViewRec& vr, const float4* __rest
     }
 }
 
+// End of a backprojection work-group. The block's gradient values g (the
+// wavefront parts in red, added in wavefront order) are finished by all
+// threads together, one output value per thread and pass, in row order:
+//   unfused: xo = scale g on the block's stage pixels;
+//   fused:   z = y_prev - (eta sigma / f^2) g on the block's f x f fine pixels
+//            (explicit fused multiply-adds: every kernel rounds this the same
+//            way), with the optional extras mu (z = y_prev - mu_scale mu -
+//            scale g) and g_out (g itself, stored once per stage pixel).
+// Fine pixel e of block (bx, by) (row-major over its bw f x bw f fine
+// pixels): stage pixel (cr, cc) within the block, fine pixel (FR, FC) in the
+// image; false if outside. The quotients use float reciprocals rf = 1 / f and
+// rfw = 1 / (bw f): a product is within (bw f) 2^-23 of the exact quotient,
+// which lies at least 1 / (2 bw f) from an integer, so the truncation is
+// exact while bw f < 2048 (bw <= 32 and f <= kMaxFactor give at most 1024).
+__device__ __forceinline__ bool bp_fine_pixel(int e, int bw, int bx, int by, int nxs, int nys, int f, float rf,
+                                              float rfw, int& cr, int& cc, int& FR, int& FC) {
+    const int fw = bw * f;
+    const int fr = (int)(((float)e + 0.5f) * rfw), fc = e - fr * fw;
+    cr = (int)(((float)fr + 0.5f) * rf);
+    cc = (int)(((float)fc + 0.5f) * rf);
+    FR = by * bw * f + fr;
+    FC = bx * bw * f + fc;
+    return by * bw + cr < nys && bx * bw + cc < nxs;
+}
+
+template <int VG, int PX, bool kFused>
+__device__ __forceinline__ void bp_finish(const float (*__restrict__ red)[PX * PX][64], int bx, int by, int nxs,
+                                          int nys, float scale, float* __restrict__ xo, int f, int nx,
+                                          const float* __restrict__ yprev, float* __restrict__ z,
+                                          const float* __restrict__ mu, float mu_scale,
+                                          float* __restrict__ g_out) {
+    constexpr int BW = 8 * PX, NT = 64 * VG;
+    const int ff = kFused ? f : 1;
+    const int n = BW * BW * ff * ff;
+    const float rf = 1.f / (float)ff, rfw = 1.f / (float)(BW * ff);
+    for (int e = threadIdx.x; e < n; e += NT) {
+        int cr, cc, FR, FC;
+        if (!bp_fine_pixel(e, BW, bx, by, nxs, nys, ff, rf, rfw, cr, cc, FR, FC)) continue;
+        const int lane = ((cr / PX) << 3) | (cc / PX), slot = (cr % PX) * PX + (cc % PX);
+        float g = red[0][slot][lane];
+        for (int w = 1; w < VG; ++w) g += red[w][slot][lane];
+        const size_t q = (size_t)(by * BW + cr) * nxs + bx * BW + cc;
+        if (!kFused) {
+            xo[q] = scale * g;
+            continue;
+        }
+        const float yp = yprev[(size_t)FR * nx + FC];
+        if (g_out && (by * BW + cr) * f == FR && (bx * BW + cc) * f == FC) g_out[q] = g;
+        const float ms = mu ? mu_scale * mu[q] : 0.f;
+        z[(size_t)FR * nx + FC] = fmaf(-scale, g, yp - ms);
+    }
+}
+
 // Work-group blk (64 VG threads) of a backprojection; views as in fp_body.
 // Fused form, optional extras: mu (a coarse gradient [nys][nxs]) enters the
 // step as z = y_prev - U(scale g + mu_scale mu); g_out receives g itself.
@@ -283,7 +336,7 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
                                         float* __restrict__ g_out = nullptr) {
     constexpr int BW = 8 * PX;  // block width in pixels
     __shared__ float4 stage[VG][kStageRays];
-    __shared__ float red[VG > 1 ? VG - 1 : 1][PX * PX][64];
+    __shared__ float red[VG][PX * PX][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int bx = blk % blocks_x, by = blk / blocks_x;
     const int c = bx * BW + PX * (lane & 7), r = by * BW + PX * (lane >> 3);
@@ -354,42 +407,14 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
             for (int base = j0 + kStageRays; base <= j1; base += kStageRays) chunk(base);
         }
     }
-    if (VG > 1) {
-        if (wave > 0) {
+    // every wavefront parks its partial sums; the work-group then finishes the
+    // block together, adding the parts in wavefront order
 #pragma unroll
-            for (int a = 0; a < PX; ++a)
+    for (int a = 0; a < PX; ++a)
 #pragma unroll
-                for (int b = 0; b < PX; ++b) red[wave - 1][a * PX + b][lane] = acc[a][b];
-        }
-        __syncthreads();
-        if (wave > 0) return;
-        for (int w = 0; w < VG - 1; ++w)
-#pragma unroll
-            for (int a = 0; a < PX; ++a)
-#pragma unroll
-                for (int b = 0; b < PX; ++b) acc[a][b] += red[w][a * PX + b][lane];
-    }
-#pragma unroll
-    for (int dr = 0; dr < PX; ++dr)
-#pragma unroll
-        for (int dc = 0; dc < PX; ++dc) {
-            const int R = r + dr, C = c + dc;
-            if (R >= nys || C >= nxs) continue;
-            if (!kFused) {
-                xo[(size_t)R * nxs + C] = scale * acc[dr][dc];
-            } else {
-                // z = y_prev - (eta sigma / f^2) g on the f x f block of (R, C)
-                // (explicit fused multiply-adds: every kernel rounds this the same way)
-                const size_t q = (size_t)R * nxs + C;
-                const float g = acc[dr][dc];
-                if (g_out) g_out[q] = g;
-                const float ms = mu ? mu_scale * mu[q] : 0.f;
-                for (int a = 0; a < f; ++a) {
-                    const size_t row = (size_t)(f * R + a) * nx + (size_t)f * C;
-                    for (int bb = 0; bb < f; ++bb) z[row + bb] = fmaf(-scale, g, yprev[row + bb] - ms);
-                }
-            }
-        }
+        for (int b = 0; b < PX; ++b) red[wave][a * PX + b][lane] = acc[a][b];
+    __syncthreads();
+    bp_finish<VG, PX, kFused>(red, bx, by, nxs, nys, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
 }
 
 // ---------------------------------------------------------------------------

@@ -12,6 +12,10 @@
 
 namespace fbpnp {
 
+// Largest pooling factor of a stage (the backprojector's epilogue takes exact
+// quotients by f with float reciprocals up to 8 x 4 x 32 fine pixels a side).
+constexpr int kMaxFactor = 32;
+
 // Zero padding on both ends of every line of the two line images of a stage.
 constexpr int kPad = 2;
 

@@ -371,7 +371,7 @@ fb_status fb_plan_create(const fb_geom* geom, int n_stages, const int32_t* facto
     if (st != FB_OK) return st;
     for (int s = 0; s < n_stages; ++s) {
         const int f = factors[s];
-        if (f < 1) return fail(FB_EINVAL, "pooling factor must be >= 1");
+        if (f < 1 || f > kMaxFactor) return fail(FB_EINVAL, "pooling factor must be in 1..32");
         if (geom->nx % f || geom->ny % f) return fail(FB_EDIV, "image size not divisible by the pooling factor");
     }
     fb_plan* p = new fb_plan();

@@ -365,6 +365,8 @@ def test_power_lipschitz_matches_oracle():
 
 def test_invalid_calls_raise_before_launch():
     gd = make_geom(**GEOMS["64"])
+    with pytest.raises(fbpnp.FbError):
+        fbpnp.Plan(fbpnp.Geometry(**gd), [64])  # factors above 32 are refused
     plan = fbpnp.Plan(fbpnp.Geometry(**gd), [1])
     x = torch.zeros(64 * 64, device="cuda")
     y = torch.zeros(90 * 96, device="cuda")
