@@ -220,14 +220,13 @@ __device__ __forceinline__ void strip_add(float p, float qf, float yy, float (&s
 // strip on a line whose offset from the middle line is kf, first centred
 // position qm.
 template <int PX>
-__device__ __forceinline__ void gather_strip(const float4* __restrict__ st, int base, int jl, int jh, float kf,
+__device__ __forceinline__ void gather_strip(const float* __restrict__ st, int base, int jl, int jh, float kf,
                                              int qm, float (&s)[PX]) {
     const float qf = (float)qm;
     // walk the staged records by address (one counter for the loop and the load)
-    const float4* const end = st + (jh - base);
-    for (const float4* e4 = st + (jl - base); e4 <= end; ++e4) {
-        const float4 e = *e4;
-        strip_add<PX>(fmaf(kf, e.y, e.x), qf, e.z, s);
+    const float* const end = st + (jh - base);
+    for (const float* e = st + (jl - base); e <= end; ++e) {
+        strip_add<PX>(fmaf(kf, e[kStageRays], e[0]), qf, e[2 * kStageRays], s);
     }
 }
 
@@ -236,7 +235,7 @@ __device__ __forceinline__ void gather_strip(const float4* __restrict__ st, int 
 // denominator of j are linear in c and r); lo..hi is the class range within
 // the staged chunk.
 template <int PX, bool kXMajor>
-__device__ __forceinline__ void bp_class(const ViewRec& vr, const float4* __restrict__ st, int base, int lo,
+__device__ __forceinline__ void bp_class(const ViewRec& vr, const float* __restrict__ st, int base, int lo,
                                                    int hi, float cc, float rc, int c, int r, int mid_c, int mid_r,
                                                    float (&acc)[PX][PX]) {
     if (lo > hi) return;
@@ -335,7 +334,9 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
                                         const float* __restrict__ mu = nullptr, float mu_scale = 0.f,
                                         float* __restrict__ g_out = nullptr) {
     constexpr int BW = 8 * PX;  // block width in pixels
-    __shared__ float4 stage[VG][kStageRays];
+    // staged rays as three arrays (position, increment, weighted residual):
+    // lanes reading entries up to 31 apart fall in different banks
+    __shared__ float stage[VG][3 * kStageRays];
     __shared__ float red[VG][PX * PX][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int bx = blk % blocks_x, by = blk / blocks_x;
@@ -351,7 +352,7 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
     for (int a = 0; a < PX; ++a)
 #pragma unroll
         for (int b = 0; b < PX; ++b) acc[a][b] = 0.f;
-    float4* st = stage[wave];
+    float* st = stage[wave];
     // this wavefront's views are i = wave + VG t, t < n_mine; lane u first
     // finds the bin footprint of view t0 + u (block corners grown by the strip
     // ends), then the wavefront walks those views one by one
@@ -389,7 +390,9 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
                 const int top = min(j1, base + kStageRays - 1);
                 for (int q = lane; q <= top - base; q += 64) {
                     const RayRec rr = rv[base + q];
-                    st[q] = make_float4(rr.pos_c, rr.dpos, yv[base + q] * rr.len, 0.f);
+                    st[q] = rr.pos_c;
+                    st[q + kStageRays] = rr.dpos;
+                    st[q + 2 * kStageRays] = yv[base + q] * rr.len;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
