@@ -37,6 +37,7 @@ FLOP_PER_BP_SAMPLE = 8      # position fma (2), fraction (1), 1-w (1), two weigh
 FLOP_PER_BP_FINE_PIXEL = 2  # z = y_prev - scale * (U g)
 FLOP_PER_TV_PIXEL_ITER = 20
 FLOP_PER_TV_PIXEL_OUT = 8
+GATHER_BYTES_PER_SAMPLE = 8  # the two 4-byte interpolation taps of a Joseph sample
 KERNEL_DESCRIPTION = {"fp": "Joseph forward projection minus b", "bp": "matched gather back-projection fused with the "
                       "gradient step", "tv": "TV-prox with relaxation, momentum and pooling epilogue"}
 KERNEL_SOURCES = ["paper_2203_07308_amd/csrc/" + f for f in
@@ -466,11 +467,12 @@ def main() -> int:
                      "bp": FLOP_PER_BP_SAMPLE * smp + FLOP_PER_BP_FINE_PIXEL * n_fine,
                      "tv": n_fine * (w.tv_iters * FLOP_PER_TV_PIXEL_ITER + FLOP_PER_TV_PIXEL_OUT)}
             for k, name in ((0, "fp"), (2, "bp"), (4, "tv")):
-                a_ = acc.setdefault((name, f), {"ms": 0.0, "n": 0, "flop": 0.0, "samples": 0})
+                a_ = acc.setdefault((name, f), {"ms": 0.0, "n": 0, "flop": 0.0, "samples": 0, "pixel_views": 0})
                 a_["ms"] += evs[t][k].elapsed_time(evs[t][k + 1])
                 a_["n"] += 1
                 a_["flop"] += flops[name]
                 a_["samples"] += smp if name != "tv" else 0
+                a_["pixel_views"] += len(sub_views[s]) * (npix // (f * f)) if name != "tv" else 0
     kernels = {}
     for (name, f), a_ in acc.items():
         sec = a_["ms"] * 1e-3
@@ -478,7 +480,13 @@ def main() -> int:
             avg_launch_us=1e3 * a_["ms"] / a_["n"], launches_per_step=a_["n"] // reps,
             us_per_step=1e3 * a_["ms"] / reps, flop_per_launch=a_["flop"] / a_["n"],
             tflops=a_["flop"] / sec / 1e12,
-            **({"gsamples_per_s": a_["samples"] / sec / 1e9} if name != "tv" else {}))
+            # projectors: exact Joseph samples per second; the conventional views x pixels
+            # per second; and the effective gather bandwidth, 8 bytes (two taps) per sample,
+            # which is on-chip traffic, not HBM bandwidth
+            **({"gsamples_per_s": a_["samples"] / sec / 1e9,
+                "conventional_gups": a_["pixel_views"] / sec / 1e9,
+                "gather_tb_per_s_effective": GATHER_BYTES_PER_SAMPLE * a_["samples"] / sec / 1e12}
+               if name != "tv" else {}))
     for k, v in kernels.items():
         log(f"  {k}: {v}")
     dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["us_per_step"])
@@ -488,6 +496,10 @@ def main() -> int:
                 "frac": round(dom["tflops"] / PEAK_FP32_TFLOPS, 5), "traffic": traffic,
                 "traffic_source": traffic_src, "avg_launch_us": round(dom["avg_launch_us"], 3),
                 "flop_per_launch": round(dom["flop_per_launch"]), "launches_timed": dom["launches_per_step"] * reps}
+    if traffic:
+        # the measured HBM rate of the dominant kernel and its share of the HBM roof
+        hbm = traffic / (dom["avg_launch_us"] * 1e-6) / 1e12
+        roofline.update(hbm_tb_per_s=round(hbm, 4), hbm_frac=round(hbm * 1e3 / PEAK_HBM_GBS, 5))
 
     # ---- time-to-PSNR: sketched vs full-gradient PnP-FISTA vs full-resolution PnP-SGD
     ttp = None
