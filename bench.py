@@ -517,8 +517,13 @@ def main() -> int:
     if not args.no_scenarios:
         scen = paper_scenarios(torch, fbpnp, synth, tune_cache)
 
-    # ---- FP64 oracle on host cores (bounded sample of the same schedule)
+    # ---- FP64 oracle on host cores (bounded sample of the same schedule), and its
+    # projectors and smaller loops beside the GPU's
     cpu = None if args.no_cpu_baseline else cpu_baseline(synth, w, xt, sk_sched, eta, n_sub)
+    odet = None
+    if not args.no_cpu_baseline:
+        odet = oracle_detail(torch, fbpnp, synth, plan, s_full, xt, tune_cache)
+        plan.autotune(n_sel=V // n_sub, cache_path=tune_cache)
 
     result = {
         "metric": "PnP iterations/s, multi-stage sketched PnP-SGD, 512^2 fan-beam",
@@ -544,6 +549,7 @@ def main() -> int:
         "time_to_psnr": ttp,
         "batched": bat,
         "paper_scenarios": scen,
+        "oracle_detail": odet,
     }
     print(json.dumps(result), flush=True)
     return 0
@@ -909,6 +915,101 @@ def cpu_baseline(synth, w, xt, sk_sched, eta, n_sub, budget_s=10.0):
     return {"value": round(iters / dt, 4), "unit": "iter/s", "cores": cores, "kind": "oracle",
             "sample": f"{runs} complete {len(sched)}-iteration sketched reconstructions of the same workload "
                       f"(FP64 C oracle, OpenMP), {dt:.2f} s"}
+
+
+def _gpu_ms(torch, fn, reps):
+    """Median over reps of one call's duration on the current stream (HIP events), after a warm-up call."""
+    fn()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times))
+
+
+def oracle_detail(torch, fbpnp, synth, plan, s_full, xt, tune_cache):
+    """The FP64 oracle beside the GPU, on the host cores and on one thread: the full-view
+    forward and back projection of the 512^2 geometry at f = 1 (one call each), and the
+    complete 64^2 PnP-ISTA and 256^2 two-stage reconstructions (all host threads)."""
+    import oracle
+
+    oracle.build(force=False)
+    w = synth.WORKLOADS["ms2g512"]
+    gd = w.geometry
+    og = oracle.Geometry(**gd)
+    V, B = gd["n_views"], gd["n_bins"]
+    samples = int(np.sum(plan.view_samples(s_full)))
+    x64 = xt.astype(np.float64)
+    y64 = np.random.default_rng(17).random((V, B))
+    n_all = oracle.set_threads(0)
+    out = {"threads_all": n_all, "samples_full_projection": samples}
+    # GPU: the same full-view launches, configured for all views
+    plan.autotune(n_sel=V, cache_path=tune_cache)
+    xd = torch.from_numpy(xt.astype(np.float32)).cuda().reshape(-1)
+    yd = torch.from_numpy(y64.astype(np.float32)).cuda().reshape(-1)
+    ybuf = torch.empty(V * B, device="cuda")
+    xbuf = torch.empty(xd.numel(), device="cuda")
+    gpu = {"fp": _gpu_ms(torch, lambda: fbpnp.fanbeam_fp(plan, s_full, xd, ybuf), 20),
+           "bp": _gpu_ms(torch, lambda: fbpnp.fanbeam_bp(plan, s_full, yd, xbuf), 20)}
+    for name, fn in (("fp", lambda: oracle.fp(og, x64)), ("bp", lambda: oracle.bp(og, y64))):
+        d = {"gpu_ms": round(gpu[name], 4), "gpu_gsamples_per_s": round(samples / (gpu[name] * 1e-3) / 1e9, 2)}
+        for th in (n_all, 1):
+            oracle.set_threads(th)
+            t0 = time.time()
+            fn()
+            dt = time.time() - t0
+            d[f"oracle_s_{th}_threads"] = round(dt, 4)
+            d[f"oracle_gsamples_per_s_{th}_threads"] = round(samples / dt / 1e9, 4)
+        oracle.set_threads(n_all)
+        out[f"{name}_full_views_f1"] = d
+    log(f"oracle projectors: {out}")
+    # whole reconstructions of the two smaller workloads: GPU graph replay against the oracle
+    loops = {}
+    for name in ("pnp64", "ms2g256"):
+        wl = synth.WORKLOADS[name]
+        g2 = wl.geometry
+        fs = [f for f, _ in wl.stages]
+        pl = fbpnp.Plan(fbpnp.Geometry(**g2), fs)
+        pl.autotune(n_sel=g2["n_views"], cache_path=tune_cache)
+        V2, B2, n2 = g2["n_views"], g2["n_bins"], g2["nx"] * g2["ny"]
+        xt2 = synth.phantom(wl)
+        ax = torch.empty(V2 * B2, device="cuda")
+        fbpnp.fanbeam_fp(pl, fs.index(1), torch.from_numpy(xt2).cuda().reshape(-1), ax)
+        eps = synth.standard_normal(synth.noise_seed(wl), (V2, B2))
+        b_np = synth.add_noise(ax.cpu().numpy().astype(np.float64).reshape(V2, B2), eps, wl.noise_kind,
+                               wl.noise_level).astype(np.float32)
+        bd = torch.from_numpy(b_np).cuda().reshape(-1)
+        eta2 = {f: 1.0 / fbpnp.power_lipschitz(pl, k, 100) for k, f in enumerate(fs)}
+        T2 = wl.n_iters
+        a2 = synth.momentum_table(T2, wl.momentum)
+        sched = [(k, f) for k, (f, n) in enumerate(wl.stages) for _ in range(n)]
+        x2 = torch.zeros(n2, device="cuda")
+        y2 = torch.zeros(n2, device="cuda")
+        steps = [fbpnp.pnp_args(pl, k, bd, y2, x2, x2, y2, eta2[f], float(a2[t]), None, 1.0, wl.alpha, wl.lam,
+                                wl.tau, wl.tv_iters) for t, (k, f) in enumerate(sched)]
+        graph = fbpnp.Graph(pl, steps)
+
+        def replay():
+            x2.zero_()
+            y2.zero_()
+            graph.launch()
+
+        gms = _gpu_ms(torch, replay, 5)
+        t0 = time.time()
+        oracle.pnp_run(oracle.Geometry(**g2), b_np.astype(np.float64), [(f, None, 1.0) for _, f in sched],
+                       np.array([eta2[f] for _, f in sched]), np.asarray(a2, dtype=np.float64), wl.alpha, wl.lam,
+                       wl.tv_iters, wl.tau)
+        ods = time.time() - t0
+        loops[name] = {"iterations": T2, "gpu_ms": round(gms, 4), "oracle_s": round(ods, 4),
+                       "oracle_threads": n_all, "gpu_over_oracle": round(ods / (gms * 1e-3), 1)}
+        graph.close()
+    out["loops"] = loops
+    log(f"oracle loops: {loops}")
+    return out
 
 
 if __name__ == "__main__":

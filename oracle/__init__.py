@@ -100,6 +100,8 @@ def _load():
         lib.orc_power_lipschitz_k.restype = d
         lib.orc_pnp_run_vr.argtypes = [gp, i32, ip, ip, ip, ip, dp, ip, dp, dp, d, d, i32, d, dp, dp, dp, dp]
         lib.orc_power_lipschitz.argtypes = [gp, i32, i32]
+        lib.orc_set_threads.argtypes = [i32]
+        lib.orc_set_threads.restype = ctypes.c_int
         lib.orc_power_lipschitz.restype = d
         lib.orc_psnr.argtypes = [dp, dp, ctypes.c_size_t]
         lib.orc_psnr.restype = d
@@ -334,6 +336,12 @@ def pnp_vjp(g: Geometry, b, schedule, eta, a, xT_bar, alpha: float = 1.0, lam: f
 def power_lipschitz(g: Geometry, f: int = 1, n_iter: int = 100, sketch: str = "pool") -> float:
     """L = ||A_s S||_2^2 by power iteration, for the step eta = 1/L (Sec. 3)."""
     return float(_load().orc_power_lipschitz_k(ctypes.byref(g.c()), SKETCHES[sketch], f, n_iter))
+
+
+def set_threads(n: int) -> int:
+    """Number of OpenMP threads for later oracle calls (n <= 0 leaves it); returns the
+    number in force before (timing support only)."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def psnr(x, ref) -> float:

@@ -41,6 +41,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int32_t nx, ny;        /* full-resolution grid (pixels) */
@@ -824,4 +827,18 @@ void orc_pnp_vjp(const orc_geom* g, int T, const int32_t* factor, const int32_t*
     free(yb);
     free(zb);
     free(hz);
+}
+
+/* Timing support (no arithmetic of the method): sets the number of OpenMP
+ * threads later calls use (n <= 0 leaves it) and returns the number in force
+ * before the call (1 when built without OpenMP). */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    const int prev = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return prev;
+#else
+    (void)n;
+    return 1;
+#endif
 }
