@@ -46,3 +46,15 @@ def test_launch_traffic_reads_matching_summary(tmp_path):
     p.write_text(f"kernel sources sha256: `{'0' * 64}`\n\n{row}\n")
     assert bench.launch_traffic("bp_f1", str(p))[0] is None
     assert bench.launch_traffic("bp_f1", os.path.join(str(tmp_path), "missing.md"))[0] is None
+
+
+def test_oracle_thread_setting_round_trips():
+    """The oracle's thread count (timing support) can be set and restored."""
+    import oracle
+
+    before = oracle.set_threads(0)
+    assert before >= 1
+    assert oracle.set_threads(1) == before
+    assert oracle.set_threads(before) == 1
+    assert oracle.set_threads(0) == before
+
