@@ -10,6 +10,8 @@ Tolerances (FP32 GPU against FP64 oracle):
   * reconstructions (whole PnP loops): relative L2 <= 1e-4.
 """
 import math
+import os
+import shutil
 import sys
 
 import numpy as np
@@ -20,6 +22,7 @@ import oracle
 from paper_2203_07308_amd import fbpnp, synth
 
 pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def say(*a):
@@ -310,8 +313,9 @@ def test_loop_ms2g256_two_stage():
     assert rel(x, ref) <= 1e-4, rel(x, ref)
 
 
-def test_loop_ms2g512_subsets_multistage():
-    """Multi-stage sketched PnP-SGD at 512^2, 1 of 8 view subsets, f = 4, 2, 1 (4 each)."""
+def test_loop_ms2g512_subsets_multistage(tmp_path):
+    """Multi-stage sketched PnP-SGD at 512^2, 1 of 8 view subsets, f = 4, 2, 1 (4 each), with the
+    built-in launch shapes and with those the benchmark runs (the shipped autotuner cache)."""
     w, gd, og, xt, b = problem("ms2g512")
     plan = fbpnp.Plan(fbpnp.Geometry(**gd), [4, 2, 1])
     seq = synth.subset_sequence(3000 * 3, 12, 8)
@@ -325,6 +329,12 @@ def test_loop_ms2g512_subsets_multistage():
     say("loop ms2g512")
     x = run_gpu(plan, gd, b, sched_g, eta, a)
     ref = oracle.pnp_run(og, b.astype(np.float64), sched_o, eta, a)
+    assert rel(x, ref) <= 1e-4, rel(x, ref)
+    cache = tmp_path / "launch_configs.txt"
+    shutil.copyfile(os.path.join(ROOT, "paper_2203_07308_amd", "tuned", "mi355x_launch_configs.txt"), cache)
+    plan.autotune(n_sel=gd["n_views"] // 8, cache_path=str(cache))
+    say("loop ms2g512 tuned", [plan.get_config(k, gd["n_views"] // 8) for k in range(3)])
+    x = run_gpu(plan, gd, b, sched_g, eta, a)
     assert rel(x, ref) <= 1e-4, rel(x, ref)
 
 
@@ -374,5 +384,7 @@ def test_invalid_calls_raise_before_launch():
         fbpnp._check(fbpnp.load().fanbeam_fp(plan.handle, 3, fbpnp._ptr(x), fbpnp._ptr(y), None, 90, None))
     with pytest.raises(fbpnp.FbError):
         fbpnp._check(fbpnp.load().fanbeam_fp(plan.handle, 0, fbpnp._ptr(x), fbpnp._ptr(y), None, 91, None))
+    with pytest.raises(fbpnp.FbError):  # an empty view selection is refused, not launched
+        fbpnp._check(fbpnp.load().fanbeam_bp(plan.handle, 0, fbpnp._ptr(y), fbpnp._ptr(x), None, 0, 1.0, None))
     with pytest.raises(ValueError):
         fbpnp.fanbeam_fp(plan, 0, x[:10], y)
