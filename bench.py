@@ -259,11 +259,14 @@ def pmc_summary(args) -> int:
         for g, j in label_dispatches(names, grids):
             per[cname]["groups"].setdefault(g, []).append((names[j], float(rows[j]["Counter_Value"])))
     cf, cw = per["FETCH_SIZE"]["factor"], per["WRITE_SIZE"]["factor"]
+    dur = trace_durations(args.trace_dir) if args.trace_dir else {}
     out += ["Calibration: a 64 MiB device-to-device copy (`__amd_rocclr_copyBuffer`) reads FETCH_SIZE = "
             f"{per['FETCH_SIZE']['copy_kib']:.0f} KiB and WRITE_SIZE = {per['WRITE_SIZE']['copy_kib']:.0f} KiB, "
             f"so bytes = FETCH_SIZE x 1024 x {cf:.4f} and WRITE_SIZE x 1024 x {cw:.4f}.", "",
+            "HBM GB/s = traffic bytes per launch / the group's average duration in the kernel trace; "
+            f"its share of the {PEAK_HBM_GBS:.0f} GB/s HBM peak beside it.", "",
             "| group | kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read bytes | written bytes | "
-            "traffic bytes per launch |", "|---|---|---|---|---|---|---|---|"]
+            "traffic bytes per launch | HBM GB/s | of HBM peak |", "|---|---|---|---|---|---|---|---|---|---|"]
     groups = per["FETCH_SIZE"]["groups"]
     for g in sorted(groups, key=lambda k: (k.split("_f")[0], -int(k.split("_f")[1]))):
         fv = [v for _, v in groups[g]]
@@ -273,8 +276,11 @@ def pmc_summary(args) -> int:
         fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)
         rb, wb = fk * 1024 * cf, wk * 1024 * cw
         kn = sorted(set(n for n, _ in groups[g]))
+        us = sum(dur[g]) / len(dur[g]) if g in dur else None
+        gbs = (rb + wb) / (us * 1e-6) / 1e9 if us else None
+        rate = "| |" if gbs is None else f"| {gbs:.0f} | {gbs / PEAK_HBM_GBS:.3f} |"
         out.append(f"| {g} | {', '.join('`' + k + '`' for k in kn)} | {len(fv)} | {fk:.1f} | {wk:.1f} | "
-                   f"{rb:.0f} | {wb:.0f} | {rb + wb:.0f} |")
+                   f"{rb:.0f} | {wb:.0f} | {rb + wb:.0f} " + rate)
     if args.counters:
         out += counter_tables(args)
     print("\n".join(out))
@@ -286,6 +292,18 @@ TV_GRID_512 = 512 * 512  # work-items of a denoiser launch on the 512^2 image (o
 
 # MI355X: 256 CUs x 4 SIMDs; a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
 N_SIMD, VALU_CYCLES, CLOCK_GHZ = 1024, 4, 2.4
+
+
+def trace_durations(trace_dir):
+    """Durations (us) of every labelled dispatch in a rocprofv3 kernel trace, per group."""
+    trace = _csv(trace_dir, "kernel_trace.csv")
+    trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+    names = [_short(r["Kernel_Name"]) for r in trace]
+    grids = [int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) for r in trace]
+    dur = {}
+    for g, j in label_dispatches(names, grids):
+        dur.setdefault(g, []).append((int(trace[j]["End_Timestamp"]) - int(trace[j]["Start_Timestamp"])) * 1e-3)
+    return dur
 
 
 def counter_tables(args):
@@ -303,14 +321,7 @@ def counter_tables(args):
             names = [_short(r["Kernel_Name"]) for r in rs]
             for g, j in label_dispatches(names, [int(r["Grid_Size"]) for r in rs]):
                 per.setdefault(g, {}).setdefault(cname, []).append(float(rs[j]["Counter_Value"]))
-    dur = {}
-    if args.trace_dir:
-        trace = _csv(args.trace_dir, "kernel_trace.csv")
-        trace.sort(key=lambda r: int(r["Start_Timestamp"]))
-        names = [_short(r["Kernel_Name"]) for r in trace]
-        grids = [int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) for r in trace]
-        for g, j in label_dispatches(names, grids):
-            dur.setdefault(g, []).append((int(trace[j]["End_Timestamp"]) - int(trace[j]["Start_Timestamp"])) * 1e-3)
+    dur = trace_durations(args.trace_dir) if args.trace_dir else {}
     cnames = sorted({c for v in per.values() for c in v})
     out = ["", "## Further counters (average per dispatch)", "",
            "| group | " + " | ".join(cnames) + " | avg us (trace) | VALU busy | L2 hit |",
