@@ -77,16 +77,20 @@ __device__ __forceinline__ void prepare_body(int bx, int by, const float* __rest
 // Buffer resource word 3 for raw (untyped) buffer loads on CDNA.
 constexpr int kBufWord3 = 0x00020000;
 
-// Wavefront-wide minimum and maximum (every lane gets the result).
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v = min(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v = max(v, __shfl_xor(v, o));
-    return v;
+// The value of lane (lane ^ o) for a power of two o < 64, by DPP lane moves
+// where one exists. kAny: any lane partner inside the same aligned group of 2o
+// lanes that lies in the other half will do (min and max reductions); else the
+// partner is exactly lane ^ o.
+template <bool kAny, typename T>
+__device__ __forceinline__ T lane_pair(T v, int o) {
+    const int iv = __builtin_bit_cast(int, v);
+    int r;
+    if (o == 1) r = __builtin_amdgcn_update_dpp(iv, iv, 0xB1, 0xF, 0xF, false);       // quad_perm 1,0,3,2
+    else if (o == 2) r = __builtin_amdgcn_update_dpp(iv, iv, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    else if (o == 4 && kAny) r = __builtin_amdgcn_update_dpp(iv, iv, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    else if (o == 8) r = __builtin_amdgcn_update_dpp(iv, iv, 0x128, 0xF, 0xF, false);  // row_ror 8
+    else r = __shfl_xor(iv, o);
+    return __builtin_bit_cast(T, r);
 }
 
 // Work-group blk (256 threads) of a projection; view i of the selection is
@@ -115,7 +119,11 @@ __device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays
     if (active) v = views ? views[i] : view0 + i * view_step;
     const bool valid = active && (unsigned)v < (unsigned)n_views;  // invalid view index: a zero row
     RayRec r{0.f, 0.f, 0.f, 0u};
-    if (valid) r = rays[(size_t)v * n_bins + j];
+    float bj = 0.f;  // b is read with the ray record, ahead of the march
+    if (valid) {
+        r = rays[(size_t)v * n_bins + j];
+        if (kResid && seg == 0) bj = b[(size_t)v * n_bins + j];
+    }
     const int lo = (int)(r.bits & 0xFFFFu), n = (int)((r.bits >> 16) & 0x7FFFu);
     const bool ymaj = (r.bits >> 31) != 0u;
     if (n == 0) {  // no samples (or no ray): every position clamps into the padding
@@ -125,8 +133,15 @@ __device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays
     // All lanes march the same lines in lockstep (the union of the wavefront's
     // sample ranges, split into SEG parts), so one load instruction reads
     // neighbouring positions of one line. Outside its own range a ray's
-    // position is clamped into the zero padding and adds nothing.
-    const int L0 = wave_min(n > 0 ? lo : 1 << 30), L1 = wave_max(n > 0 ? lo + n : -(1 << 30));
+    // position is clamped into the zero padding and adds nothing. The SEG
+    // lanes of a ray hold the same record, so the range is reduced over the R
+    // lanes of one segment.
+    int L0 = n > 0 ? lo : 1 << 30, L1 = n > 0 ? lo + n : -(1 << 30);
+#pragma unroll
+    for (int o = 1; o < R; o <<= 1) {
+        L0 = min(L0, lane_pair<true>(L0, o));
+        L1 = max(L1, lane_pair<true>(L1, o));
+    }
     float acc = 0.f;
     if (L1 > L0) {
         const int la = L0 + ((L1 - L0) * seg) / SEG, lb = L0 + ((L1 - L0) * (seg + 1)) / SEG;
@@ -152,14 +167,14 @@ __device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays
     }
     // fixed-order sum of the SEG partial sums of each ray
 #pragma unroll
-    for (int o = R; o < 64; o <<= 1) acc += __shfl_xor(acc, o);
+    for (int o = R; o < 64; o <<= 1) acc += lane_pair<false>(acc, o);
     if (active && seg == 0) {
         float val = 0.f;
         if (valid) {
             // the residual as an explicit fused multiply-add, so every kernel rounds it alike
             const float p = acc * r.len;
             if (proj_out) proj_out[(size_t)v * n_bins + j] = p;
-            val = kResid ? fmaf(acc, r.len, -b[(size_t)v * n_bins + j]) : p;
+            val = kResid ? fmaf(acc, r.len, -bj) : p;
         }
         y[(size_t)i * n_bins + j] = val;
     }
