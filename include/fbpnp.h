@@ -59,7 +59,12 @@ typedef int fb_status;
 #define FB_EHIP (-5)    /* HIP runtime or launch error (message holds the HIP text) */
 #define FB_ENOMEM (-6)  /* device allocation failed (plan or graph creation only) */
 
-/* Fan-beam geometry of the full-resolution grid. */
+/* Fan-beam geometry of the full-resolution grid. Valid (FB_EGEOM otherwise):
+ * finite values; positive pixel, distances and pitch; image circumradius
+ * h sqrt(nx^2 + ny^2) / 2 < sod_mm; detector half-extent
+ * |(n_bins - 1) / 2 det_pitch_mm| + |det_offset_mm| < sdd_mm, so the fan is
+ * narrower than 90 degrees and each view's bins of one dominance class are
+ * contiguous. */
 typedef struct fb_geom {
     int32_t nx, ny;          /* image width (columns) and height (rows) */
     double pixel_mm;         /* pixel size h */

@@ -37,16 +37,25 @@ import numpy as np
 # ----------------------------------------------------------------------------------
 
 def fan_geometry(n: int, n_views: int, n_bins: int | None = None, angle_range: float = 2 * math.pi,
-                 iso_pitch_px: float = 1.0) -> dict:
+                 iso_pitch_px: float = 1.0, sod_over_radius: float | None = None) -> dict:
     """Geometry parameters for an n x n grid of 1 mm pixels; a detector bin spans
-    iso_pitch_px pixels at the isocentre."""
+    iso_pitch_px pixels at the isocentre.
+    sod_over_radius: a wide fan instead, with the source at that multiple of the
+    image's circumradius and the bins spread over the fan that covers the image."""
     h = 1.0
+    nb = int(round(1.5 * n)) if n_bins is None else n_bins
     sod = 7.8125 * n * h
     sdd = 2.0 * sod
+    pitch = iso_pitch_px * h * sdd / sod
+    if sod_over_radius is not None:
+        radius = n * h / math.sqrt(2.0)
+        sod = sod_over_radius * radius
+        sdd = 2.0 * sod
+        half_fan = math.asin(radius / sod)
+        pitch = 1.02 * 2.0 * sdd * math.tan(half_fan) / nb
     return dict(
-        nx=n, ny=n, pixel_mm=h, n_views=n_views,
-        n_bins=int(round(1.5 * n)) if n_bins is None else n_bins,
-        sod_mm=sod, sdd_mm=sdd, det_pitch_mm=iso_pitch_px * h * sdd / sod, det_offset_mm=0.0,
+        nx=n, ny=n, pixel_mm=h, n_views=n_views, n_bins=nb,
+        sod_mm=sod, sdd_mm=sdd, det_pitch_mm=pitch, det_offset_mm=0.0,
         angle0_rad=0.0, angle_step_rad=angle_range / n_views,
     )
 

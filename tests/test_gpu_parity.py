@@ -53,8 +53,8 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def make_geom(n, V, nb=None, ny=None, **kw):
-    g = synth.fan_geometry(n, V, nb)
+def make_geom(n, V, nb=None, ny=None, wide=None, **kw):
+    g = synth.fan_geometry(n, V, nb, sod_over_radius=wide)
     if ny is not None:
         g["ny"] = ny
     g.update(kw)
@@ -75,6 +75,8 @@ GEOMS = {
     "ragged": dict(n=70, V=37, nb=101, ny=52, det_offset_mm=1.3, angle0_rad=0.2),
     "diag": dict(n=40, V=8, angle0_rad=math.pi / 4),
     "tiny": dict(n=8, V=4, nb=12),
+    # source at 1.5 image circumradii: a fan of about 85 degrees (the plan's limit is 90)
+    "widefan": dict(n=128, V=90, nb=256, wide=1.5),
 }
 
 FP_CASES = [
@@ -84,6 +86,7 @@ FP_CASES = [
     ("1024", 1, None),
     ("ragged", 1, None), ("ragged", 2, ("list", [36, 0, 17, 17, 5])),
     ("diag", 1, None), ("diag", 2, None), ("tiny", 1, None), ("tiny", 2, ("list", [2])),
+    ("widefan", 1, None), ("widefan", 2, None), ("widefan", 4, ("sub", 1, 4)),
 ]
 
 
@@ -157,7 +160,7 @@ def test_fanbeam_bp_skips_invalid_views():
         assert rel(host(x).reshape(ref.shape), ref) <= 1e-5, form
 
 
-@pytest.mark.parametrize("name,f", [("256", 1), ("512", 4), ("ragged", 2), ("512", 1)])
+@pytest.mark.parametrize("name,f", [("256", 1), ("512", 4), ("ragged", 2), ("512", 1), ("widefan", 1)])
 def test_fp32_adjoint_identity(name, f):
     """<A x, y> = <x, A^T y> between the GPU projector and the GPU backprojector (each launch shape)."""
     gd, og, plan, _ = setup_case(name, f, None)
@@ -177,18 +180,22 @@ def test_fp32_adjoint_identity(name, f):
         assert abs(lhs - rhs) <= 1e-5 * abs(lhs), form
 
 
-def test_stage_sample_counts_match_oracle():
-    gd = make_geom(**GEOMS["256"])
+@pytest.mark.parametrize("name", ["256", "widefan"])
+def test_stage_sample_counts_match_oracle(name):
+    gd = make_geom(**GEOMS[name])
+    n = gd["nx"]
     plan = fbpnp.Plan(fbpnp.Geometry(**gd), [1, 2, 4])
     og = oracle.Geometry(**gd)
     for s, f in enumerate([1, 2, 4]):
         info = plan.stage_info(s)
-        assert (info.factor, info.nxs, info.nys) == (f, 256 // f, 256 // f)
+        assert (info.factor, info.nxs, info.nys) == (f, n // f, n // f)
         ref = oracle.count_samples(og, f)
-        assert abs(info.samples_all_views - ref) <= 1e-6 * ref
+        # the plan decides validity in the kernels' FP32 evaluation of the position:
+        # a few samples within one rounding of the grid edge (weight ~0) may differ
+        assert abs(info.samples_all_views - ref) <= 4 + 1e-6 * ref, (f, info.samples_all_views, ref)
         per_view = plan.view_samples(s)
         assert sum(per_view) == info.samples_all_views
-        for k in (0, 17, 100, gd["n_views"] - 1):
+        for k in (0, 17, gd["n_views"] // 2 + 1, gd["n_views"] - 1):
             rk = oracle.count_samples(og, f, np.array([k], dtype=np.int32))
             assert abs(per_view[k] - rk) <= 2 + 1e-5 * rk, (f, k, per_view[k], rk)
 

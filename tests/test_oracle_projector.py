@@ -49,10 +49,15 @@ def ellipse_integrals(e, geo, views):
     return np.array(res)
 
 
-def test_disk_chord_closed_form():
+# source at 1.5 image circumradii: a fan of about 85 degrees (the plan's limit is 90)
+WIDE = 1.5
+
+
+@pytest.mark.parametrize("wide", [None, WIDE])
+def test_disk_chord_closed_form(wide):
     """A centred disk of radius R and density 1: integral 2 sqrt(R^2 - s^2) at distance s."""
     n = 128
-    geo = synth.fan_geometry(n, 8)
+    geo = synth.fan_geometry(n, 8, None if wide is None else 256, sod_over_radius=wide)
     R = 40.0
     e = synth.Ellipses(np.zeros(1), np.zeros(1), np.full(1, R), np.full(1, R), np.zeros(1), np.ones(1))
     an = ellipse_integrals(e, geo, range(8))
@@ -81,14 +86,15 @@ def test_ellipse_integrals_converge_first_order():
     assert errs[-1] < 0.01, errs
 
 
-@pytest.mark.parametrize("n,f", [(32, 1), (48, 1), (64, 2), (64, 4)])
-def test_affine_image_exact_on_interior_rays(n, f):
+@pytest.mark.parametrize("n,f,wide", [(32, 1, None), (48, 1, None), (64, 2, None), (64, 4, None),
+                                      (48, 1, WIDE), (64, 2, WIDE)])
+def test_affine_image_exact_on_interior_rays(n, f, wide):
     """For X = a + b x + c y at pixel centres, Joseph's sum equals the exact integral of
     the affine function over the chord between the outer pixel edges of the sampled axis,
     on every ray whose interpolation never leaves the grid (midpoint rule and linear
     interpolation are both exact for affine functions)."""
     V = 16
-    geo = synth.fan_geometry(n, V)
+    geo = synth.fan_geometry(n, V, None if wide is None else 2 * n, sod_over_radius=wide)
     g = oracle.Geometry(**geo)
     ns, hs = n // f, f * geo["pixel_mm"]
     a0, bx, cy = 0.7, 0.013, -0.021
@@ -150,11 +156,13 @@ def test_linearity_and_zero():
                                rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("n,V,f,sub", [(64, 90, 1, None), (64, 90, 2, None), (64, 90, 4, None),
-                                       (48, 30, 2, [1, 4, 7, 29]), (40, 36, 1, [35, 0, 17])])
-def test_transpose_identity(n, V, f, sub):
+@pytest.mark.parametrize("n,V,f,sub,wide", [(64, 90, 1, None, None), (64, 90, 2, None, None),
+                                            (64, 90, 4, None, None), (48, 30, 2, [1, 4, 7, 29], None),
+                                            (40, 36, 1, [35, 0, 17], None), (48, 30, 1, None, WIDE),
+                                            (48, 30, 4, [2, 9, 0], WIDE)])
+def test_transpose_identity(n, V, f, sub, wide):
     """<M A_s x, y> = <x, (M A_s)^T y> to 1e-12 relative."""
-    geo = synth.fan_geometry(n, V)
+    geo = synth.fan_geometry(n, V, None if wide is None else 2 * n, sod_over_radius=wide)
     g = oracle.Geometry(**geo)
     rng = np.random.default_rng(11)
     x = rng.standard_normal((n // f, n // f))
@@ -190,10 +198,11 @@ def test_subset_rows_are_rows_of_full_projection():
     np.testing.assert_array_equal(oracle.fp(g, x, 1, sub), full[sub])
 
 
-def test_sample_count_brute_force():
+@pytest.mark.parametrize("wide", [None, WIDE])
+def test_sample_count_brute_force(wide):
     """Count of in-grid samples against a direct enumeration with the independent rays."""
     n, V = 24, 8
-    geo = synth.fan_geometry(n, V)
+    geo = synth.fan_geometry(n, V, None if wide is None else 48, sod_over_radius=wide)
     g = oracle.Geometry(**geo)
     ctr = (np.arange(n) - 0.5 * (n - 1))
     total = 0
