@@ -345,6 +345,29 @@ def test_loop_ms2g512_subsets_multistage(tmp_path):
     assert rel(x, ref) <= 1e-4, rel(x, ref)
 
 
+def test_loop_widefan_two_stage_subsets():
+    """Sketched PnP-SGD on the 85-degree fan: 8 iterations at f = 2, then 8 at f = 1, 1 of 3 view
+    subsets (sigma = 3), FISTA momentum, against the oracle's loop."""
+    gd = make_geom(**GEOMS["widefan"])
+    og = oracle.Geometry(**gd)
+    xt = ellipse_image(gd["ny"], gd["nx"], 21)
+    ax = oracle.fp(og, xt.astype(np.float64))
+    b = (ax + 0.01 * ax.max() * synth.standard_normal(77, ax.shape)).astype(np.float32)
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [2, 1])
+    L2, L1 = oracle.power_lipschitz(og, 2, 40), oracle.power_lipschitz(og, 1, 40)
+    T = 16
+    seq = synth.subset_sequence(91, T, 3)
+    fs = [2] * 8 + [1] * 8
+    sched_o = [(fs[t], synth.subset_views(seq[t], 3, gd["n_views"]), 3.0) for t in range(T)]
+    sched_g = [({2: 0, 1: 1}[fs[t]], sched_o[t][1], 3.0) for t in range(T)]
+    eta = np.array([1 / L2 if f == 2 else 1 / L1 for f in fs])
+    a = synth.momentum_table(T)
+    say("loop widefan")
+    x = run_gpu(plan, gd, b, sched_g, eta, a)
+    ref = oracle.pnp_run(og, b.astype(np.float64), sched_o, eta, a)
+    assert rel(x, ref) <= 1e-4, rel(x, ref)
+
+
 def test_graph_replay_equals_eager_and_is_deterministic():
     w, gd, og, xt, b = problem("pnp64")
     plan = fbpnp.Plan(fbpnp.Geometry(**gd), [2, 1])
