@@ -451,9 +451,16 @@ fb_status pnp_step_batched(fb_batch* B, const fb_batch_args* a, hipStream_t stre
     // lambda == 0 or no TV iterations: the TV kernel only relaxes and applies momentum
     const float lam = a->lambda > 0.f ? a->lambda : 1.f;
     const int iters = a->lambda > 0.f ? a->tv_iters : 0;
-    TimedLaunch tl(a->events, 4);
-    return launch_tv_batch(B, a->next_stage, lam, a->tau, iters, a->alpha, a->a_t, a->x_prev, a->x_out, a->y_out,
-                           a->history, c.tv_tile, stream);
+    // the next stage's pooling goes into the TV epilogue when its factor
+    // divides the TV tile, else into a pooling launch after it
+    const bool pool_after = a->next_stage >= 0 && c.tv_tile % B->factors[a->next_stage] != 0;
+    {
+        TimedLaunch tl(a->events, 4);
+        if ((st = launch_tv_batch(B, pool_after ? -1 : a->next_stage, lam, a->tau, iters, a->alpha, a->a_t,
+                                  a->x_prev, a->x_out, a->y_out, a->history, c.tv_tile, stream)) != FB_OK)
+            return st;
+    }
+    return pool_after ? launch_prepare_batch(B, a->next_stage, a->y_out, stream) : FB_OK;
 }
 
 fb_status fb_batch_graph_create(fb_batch* B, const fb_batch_args* steps, int n_steps, fb_graph** out) {

@@ -565,13 +565,34 @@ static PoolTarget pool_target(const fb_plan* p, int next_stage) {
     return pt;
 }
 
+// The denoiser of a step on z (p->zbuf). With next_stage set, y_t is pooled
+// for that stage in the TV kernel's epilogue when its factor divides the TV
+// tile, else by a pooling launch after it. lambda == 0 or no TV iterations:
+// D is the identity, and the same kernel only applies the relaxation and the
+// momentum (div p = 0).
+static fb_status step_tv(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
+    const int tile = plan_config(p, a->stage, a->n_sel).tv_tile;
+    PoolTarget pt = pool_target(p, a->next_stage);
+    const bool pool_after = pt.f > 0 && tile % pt.f != 0;
+    if (pool_after) pt = PoolTarget();
+    const float lam = a->lambda > 0.f ? a->lambda : 1.f;
+    const int iters = a->lambda > 0.f ? a->tv_iters : 0;
+    fb_status st;
+    {
+        TimedLaunch tl(a->events, 4);
+        st = launch_tv_single(p->zbuf, p->g.nx, p->g.ny, lam, a->tau, iters, nullptr, nullptr, 1, a->alpha, a->a_t,
+                              a->x_prev, a->x_out, a->y_out, a->history, stream, pt, tile);
+    }
+    if (st != FB_OK || !pool_after) return st;
+    return launch_prepare(p, a->next_stage, a->y_out, p->g.nx, p->stages[a->next_stage].f, stream);
+}
+
 // pnp_step at a stage with the bicubic sketch: S into the line images, the
 // residual projection, the back-projection into the coarse gradient g, then
 // z = y_{t-1} - eta sigma S^T g and the denoiser.
 static fb_status pnp_step_bicubic(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
     fb_status st;
     if (a->vr_mode != 0) return fail(FB_EINVAL, "pnp_step: variance reduction is defined with the pooling sketch");
-    const int nx = p->g.nx, ny = p->g.ny;
     if ((st = launch_bicubic_down(p, a->stage, a->y_prev, nullptr, stream)) != FB_OK) return st;
     {
         TimedLaunch tl(a->events, 0);
@@ -585,12 +606,7 @@ static fb_status pnp_step_bicubic(const fb_plan* p, const fb_pnp_args* a, hipStr
     }
     if ((st = launch_bicubic_up(p, a->stage, p->sk_g, a->eta * a->sigma, a->y_prev, p->zbuf, stream)) != FB_OK)
         return st;
-    const float lam = a->lambda > 0.f ? a->lambda : 1.f;
-    const int iters = a->lambda > 0.f ? a->tv_iters : 0;
-    TimedLaunch tl(a->events, 4);
-    return launch_tv_single(p->zbuf, nx, ny, lam, a->tau, iters, nullptr, nullptr, 1, a->alpha, a->a_t, a->x_prev,
-                            a->x_out, a->y_out, a->history, stream, pool_target(p, a->next_stage),
-                            plan_config(p, a->stage, a->n_sel).tv_tile);
+    return step_tv(p, a, stream);
 }
 
 fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
@@ -611,9 +627,8 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
     if (a->vr_mode == 1 && a->n_sel != p->g.n_views)
         return fail(FB_ESUBSET, "pnp_step: a snapshot step uses every view");
     const Stage& S = p->stages[a->stage];
-    const int nx = p->g.nx, ny = p->g.ny;
     if (bicubic_stage(p, a->stage)) return pnp_step_bicubic(p, a, stream);
-    if (!a->prepared && (st = launch_prepare(p, a->stage, a->y_prev, nx, S.f, stream)) != FB_OK) return st;
+    if (!a->prepared && (st = launch_prepare(p, a->stage, a->y_prev, p->g.nx, S.f, stream)) != FB_OK) return st;
     // variance-reduced modes: 1 records the snapshot's projection and coarse
     // gradient; 2 projects against the snapshot's projection and adds its gradient
     const bool snap = a->vr_mode == 1, vr = a->vr_mode == 2;
@@ -631,14 +646,7 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
                                     snap ? a->snap_grad : nullptr)) != FB_OK)
             return st;
     }
-    const PoolTarget pt = pool_target(p, a->next_stage);
-    // lambda == 0 or no TV iterations: D is the identity, the same kernel then
-    // only applies the relaxation and momentum (div p = 0)
-    const float lam = a->lambda > 0.f ? a->lambda : 1.f;
-    const int iters = a->lambda > 0.f ? a->tv_iters : 0;
-    TimedLaunch tl(a->events, 4);
-    return launch_tv_single(p->zbuf, nx, ny, lam, a->tau, iters, nullptr, nullptr, 1, a->alpha, a->a_t, a->x_prev,
-                            a->x_out, a->y_out, a->history, stream, pt, plan_config(p, a->stage, a->n_sel).tv_tile);
+    return step_tv(p, a, stream);
 }
 
 fb_status fb_graph_create(const fb_plan* p, const fb_pnp_args* steps, int n_steps, fb_graph** out) {

@@ -44,9 +44,9 @@ SLICES = [(96, 90), (64, 47), (128, 120), (48, 60), (80, 90)]
 FACTORS = [2, 1]
 
 
-def make_batch(slices=SLICES, seed=40):
+def make_batch(slices=SLICES, seed=40, factors=FACTORS):
     gds = [synth.fan_geometry(n, V) for n, V in slices]
-    batch = fbpnp.Batch([fbpnp.Geometry(**g) for g in gds], FACTORS)
+    batch = fbpnp.Batch([fbpnp.Geometry(**g) for g in gds], factors)
     xts, bs = [], []
     for i, g in enumerate(gds):
         n = g["nx"]
@@ -75,12 +75,12 @@ def schedule(n_f2=3, n_f1=3, n_sub=3):
     return out
 
 
-def etas(batch, gds):
+def etas(batch, gds, factors=FACTORS):
     """Per (stage, slice) step sizes 1/L from the slices' own plans."""
-    e = np.zeros((len(FACTORS), len(gds)), dtype=np.float32)
+    e = np.zeros((len(factors), len(gds)), dtype=np.float32)
     for i in range(len(gds)):
         p = batch.slice_plan(i)
-        for k in range(len(FACTORS)):
+        for k in range(len(factors)):
             e[k, i] = 1.0 / fbpnp.power_lipschitz(p, k, 30)
     return e
 
@@ -110,8 +110,8 @@ def run_batched(batch, b_arena, sched, eta, graph=False, alpha=1.0):
     return x
 
 
-def run_single(g, b, sched, eta_i, cfgs, alpha=1.0):
-    plan = fbpnp.Plan(fbpnp.Geometry(**g), FACTORS)
+def run_single(g, b, sched, eta_i, cfgs, alpha=1.0, factors=FACTORS):
+    plan = fbpnp.Plan(fbpnp.Geometry(**g), factors)
     for k, c in enumerate(cfgs):
         plan.set_config(k, c)
     npix = g["nx"] * g["ny"]
@@ -150,6 +150,32 @@ def test_batched_graph_equals_direct_calls():
     xe = host(run_batched(batch, b_arena, sched, eta))
     xg = host(run_batched(batch, b_arena, sched, eta, graph=True))
     np.testing.assert_array_equal(xe, xg)
+
+
+def test_batched_factor_not_dividing_the_tv_tile():
+    """Stage factors 3 and 1: 3 divides neither TV tile, so a step followed by a step at f = 3 pools
+    y_t in a launch of its own after the denoiser instead of in its epilogue. Graph replays equal
+    direct chained calls and single-slice runs, and a slice matches the oracle's loop."""
+    factors = [3, 1]
+    gds, batch, xts, bs, b_arena = make_batch(slices=[(48, 30), (96, 47)], seed=95, factors=factors)
+    sched = schedule(4, 3, 3)
+    eta = etas(batch, gds, factors)
+    say("batched factor 3")
+    xd = run_batched(batch, b_arena, sched, eta)
+    xg = host(run_batched(batch, b_arena, sched, eta, graph=True))
+    np.testing.assert_array_equal(host(xd), xg)
+    cfgs = [batch.get_config(k, 3 if k == 0 else 1) for k in range(len(factors))]
+    for i, g in enumerate(gds):
+        ref = run_single(g, bs[i], sched, eta[:, i], cfgs, factors=factors)
+        np.testing.assert_array_equal(host(batch.image(xd, i)), ref)
+    og = oracle.Geometry(**gds[0])
+    so = [(factors[k], None if n_sub <= 1 else synth.subset_views(sub, n_sub, gds[0]["n_views"]), sigma)
+          for k, n_sub, sub, sigma, _ in sched]
+    et = np.array([eta[k, 0] for k, *_ in sched], dtype=np.float64)
+    a = np.array([s[4] for s in sched])
+    ref = oracle.pnp_run(og, bs[0].astype(np.float64), so, et, a)
+    got = host(batch.image(xd, 0))
+    assert rel(got, ref) <= 1e-4, rel(got, ref)
 
 
 def test_batched_slice_matches_oracle_loop():

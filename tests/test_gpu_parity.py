@@ -289,6 +289,38 @@ def test_pnp_step_matches_oracle_iterations():
     assert rel(x, ref) <= 2e-5
 
 
+@pytest.mark.parametrize("form", BP_FORMS)
+def test_pnp_step_large_odd_pooling_factors(form):
+    """Fused steps at f = 30, 24 and 5 on a 240 x 120 grid (stage grids 8 x 4, 10 x 5 and 48 x 24,
+    ragged pixel blocks): the back-projector epilogue takes exact quotients by f and by the block
+    width in fine pixels for factors that are not powers of two, up to blocks of 32 x 30 fine
+    pixels."""
+    gd = make_geom(n=240, V=24, ny=120)
+    og = oracle.Geometry(**gd)
+    xt = ellipse_image(gd["ny"], gd["nx"], 9)
+    b = oracle.fp(og, xt.astype(np.float64)).astype(np.float32)
+    factors = [30, 24, 5]
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), factors)
+    for k in range(3):
+        plan.set_config(k, form)
+    order = [0, 1, 2, 0, 2]
+    sched_g = [(k, None, 1.0) for k in order]
+    sched_o = [(factors[k], None, 1.0) for k in order]
+    eta = np.array([1.0 / oracle.power_lipschitz(og, factors[k], 40) for k in order])
+    a = synth.momentum_table(len(order))
+    say("pnp_step large factors", form)
+    x, hist = run_gpu(plan, gd, b, sched_g, eta, a, history=True)
+    ref, rhist = oracle.pnp_run(og, b.astype(np.float64), sched_o, eta, a, history=True)
+    for t in range(len(order)):
+        got = hist[t].reshape(ref.shape)
+        assert rel(got, rhist[t]) <= 2e-5, (t, rel(got, rhist[t]))
+    # chained steps pool y_t for the next stage after the denoiser: in its epilogue when the
+    # factor divides the TV tile, else by a pooling launch of their own (30 and 24 divide neither)
+    say("pnp_step large factors, chained and graph", form)
+    np.testing.assert_array_equal(run_gpu(plan, gd, b, sched_g, eta, a, chained=True), x)
+    np.testing.assert_array_equal(run_gpu(plan, gd, b, sched_g, eta, a, graph=True), x)
+
+
 def oracle_step(og, f):
     return 1.0 / oracle.power_lipschitz(og, f, 100)
 
