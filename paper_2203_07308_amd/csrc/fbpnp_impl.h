@@ -24,8 +24,9 @@ constexpr int kPad = 2;
 //   pos(k) = npos/2 + fmaf(k - nlines/2, dpos, pos_c)     (integer npos/2, nlines/2)
 // with nlines, npos the grid sizes along the major and minor axis. The plan
 // chooses lo, n so that, with exactly this float evaluation, a line has a
-// sample if and only if pos(k) lies in [-1, npos). Ray weight
-// len = f h |d| / |d_major|.
+// sample if and only if pos(k) lies in [-1, npos); a ray without samples
+// (n = 0) keeps its pos_c and dpos, so pos(k) lies outside that interval on
+// every line of the grid. Ray weight len = f h |d| / |d_major|.
 // bits: lo (16) | n (15) << 16 | axis << 31, axis 0 = x-major (lines are
 // columns, positions are rows), 1 = y-major (lines are rows, positions are
 // columns).

@@ -144,19 +144,18 @@ fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays,
             valid_range(p0, dp, nlines, -1.0 - margin, (double)npos + margin, lo, hi);
             while (hi >= lo && !ok32(lo)) ++lo;
             while (hi >= lo && !ok32(hi)) --hi;
+            // A ray without samples keeps its own position: then on every line of
+            // the grid it lies outside [-1, npos), which the matched back-projector
+            // relies on for every candidate ray.
             RayRec& r = rays[(size_t)k * nb + j];
+            r.pos_c = pcf;
+            r.dpos = dpf;
+            r.len = (float)w;
+            r.bits = xmajor ? 0u : 0x80000000u;
             if (hi >= lo) {
                 const int n = hi - lo + 1;
-                r.pos_c = pcf;
-                r.dpos = dpf;
-                r.len = (float)w;
-                r.bits = (uint32_t)lo | ((uint32_t)n << 16) | (xmajor ? 0u : 0x80000000u);
+                r.bits |= (uint32_t)lo | ((uint32_t)n << 16);
                 view_samples[k] += n;
-            } else {
-                r.pos_c = 0.f;
-                r.dpos = 0.f;
-                r.len = (float)w;
-                r.bits = xmajor ? 0u : 0x80000000u;
             }
         }
         // each dominance class must be one contiguous bin range
