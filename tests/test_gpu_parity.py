@@ -77,6 +77,9 @@ GEOMS = {
     "tiny": dict(n=8, V=4, nb=12),
     # source at 1.5 image circumradii: a fan of about 85 degrees (the plan's limit is 90)
     "widefan": dict(n=128, V=90, nb=256, wide=1.5),
+    # 0.15 pixel per bin at the isocentre: a 32-pixel block's footprint spans about 200 bins,
+    # more than the back-projector stages per view at once (several chunks per view)
+    "finepitch": dict(n=96, V=12, nb=640, det_pitch_mm=0.3),
 }
 
 FP_CASES = [
@@ -87,6 +90,7 @@ FP_CASES = [
     ("ragged", 1, None), ("ragged", 2, ("list", [36, 0, 17, 17, 5])),
     ("diag", 1, None), ("diag", 2, None), ("tiny", 1, None), ("tiny", 2, ("list", [2])),
     ("widefan", 1, None), ("widefan", 2, None), ("widefan", 4, ("sub", 1, 4)),
+    ("finepitch", 1, None), ("finepitch", 2, ("sub", 1, 3)),
 ]
 
 
@@ -160,7 +164,8 @@ def test_fanbeam_bp_skips_invalid_views():
         assert rel(host(x).reshape(ref.shape), ref) <= 1e-5, form
 
 
-@pytest.mark.parametrize("name,f", [("256", 1), ("512", 4), ("ragged", 2), ("512", 1), ("widefan", 1)])
+@pytest.mark.parametrize("name,f", [("256", 1), ("512", 4), ("ragged", 2), ("512", 1), ("widefan", 1),
+                                    ("finepitch", 1)])
 def test_fp32_adjoint_identity(name, f):
     """<A x, y> = <x, A^T y> between the GPU projector and the GPU backprojector (each launch shape)."""
     gd, og, plan, _ = setup_case(name, f, None)
