@@ -38,7 +38,10 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("n,ny,factors", [(64, None, [2, 4]), (512, None, [4, 2]), (96, 60, [3, 2]), (16, None, [8])])
+# the last three have stage axes of 1 to 4 pixels, shorter than the kernel's window of 4 f inputs,
+# so the half-sample reflection folds more than once
+@pytest.mark.parametrize("n,ny,factors", [(64, None, [2, 4]), (512, None, [4, 2]), (96, 60, [3, 2]), (16, None, [8]),
+                                          (9, 3, [3]), (12, 6, [6, 3]), (10, None, [5])])
 def test_bicubic_sketch_and_adjoint_match_oracle(n, ny, factors):
     g = synth.fan_geometry(n, 8)
     if ny is not None:
