@@ -72,14 +72,14 @@ def make_problem(n, V, nb, seed, nslices=1):
     return gd, og, xts, bs
 
 
-def schedule(gd, n_f2, n_f1, subsets):
-    """Two-stage schedule (f = 2 then f = 1) with FISTA momentum and optional subsets."""
+def schedule(gd, n_f2, n_f1, subsets, fc=2):
+    """Two-stage schedule (f = fc, default 2, then f = 1) with FISTA momentum and optional subsets."""
     T = n_f2 + n_f1
     a = synth.momentum_table(T)
     seq = synth.subset_sequence(77, T, subsets) if subsets else None
     sched_o, specs = [], []
     for t in range(T):
-        f, stage = (2, 0) if t < n_f2 else (1, 1)
+        f, stage = (fc, 0) if t < n_f2 else (1, 1)
         views = None if seq is None else synth.subset_views(int(seq[t]), subsets, gd["n_views"])
         sigma = float(subsets) if subsets else 1.0
         sched_o.append((f, views, sigma))
@@ -87,9 +87,9 @@ def schedule(gd, n_f2, n_f1, subsets):
     return sched_o, specs, a
 
 
-def run_case(gd, og, xt, b, n_f2, n_f1, subsets, x0, eta):
-    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [2, 1])
-    sched_o, specs, a = schedule(gd, n_f2, n_f1, subsets)
+def run_case(gd, og, xt, b, n_f2, n_f1, subsets, x0, eta, fc=2):
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [fc, 1])
+    sched_o, specs, a = schedule(gd, n_f2, n_f1, subsets, fc)
     x0_t = dev(x0).requires_grad_(True)
     eta_t = torch.tensor(eta, dtype=torch.float32, device="cuda", requires_grad=True)
     xT = unrolled_pnp(plan, dev(b).reshape(-1), specs, x0_t, eta_t)
@@ -123,6 +123,19 @@ def test_unrolled_gradients_match_oracle_small():
         e[t] = h * eta[t]
         fd = (loss(x0, eta + e) - loss(x0, eta - e)) / (2 * e[t])
         assert abs(fd - g_eta[t]) <= 1e-3 * max(abs(fd), 1e-6 * np.abs(r_eta).max()), (t, fd, g_eta[t])
+
+
+def test_unrolled_gradients_coarse_factor_three():
+    """8 unrolled iterations at 60^2, 4 at f = 3 then 4 at f = 1, 1 of 5 view subsets: the reverse
+    pass pools and back-projects with a factor that divides neither TV tile."""
+    gd, og, xts, bs = make_problem(60, 45, 90, 13)
+    L = oracle.power_lipschitz(og, 1, 50)
+    eta = np.full(8, 1.0 / L)
+    x0 = np.zeros((60, 60))
+    say("unrolled 60, f = 3")
+    g_x0, g_eta, r_x0, r_eta, *_ = run_case(gd, og, xts[0], bs[0], 4, 4, 5, x0, eta, fc=3)
+    assert rel(g_x0, r_x0) <= 1e-3, rel(g_x0, r_x0)
+    assert rel(g_eta, r_eta) <= 1e-3, (g_eta, r_eta)
 
 
 @pytest.mark.slow
