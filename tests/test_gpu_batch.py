@@ -44,13 +44,17 @@ SLICES = [(96, 90), (64, 47), (128, 120), (48, 60), (80, 90)]
 FACTORS = [2, 1]
 
 
-def make_batch(slices=SLICES, seed=40, factors=FACTORS):
+def make_batch(slices=SLICES, seed=40, factors=FACTORS, heights=None):
+    """slices: (width, views); heights: optional image heights (default square)."""
     gds = [synth.fan_geometry(n, V) for n, V in slices]
+    for g, h in zip(gds, heights or []):
+        g["ny"] = h
     batch = fbpnp.Batch([fbpnp.Geometry(**g) for g in gds], factors)
     xts, bs = [], []
     for i, g in enumerate(gds):
         n = g["nx"]
-        xt = synth.rasterise(synth.random_ellipses(seed + i, 10, n), n)
+        m = max(n, g["ny"])
+        xt = synth.rasterise(synth.random_ellipses(seed + i, 10, m), m)[:g["ny"], :n].copy()
         ax = oracle.fp(oracle.Geometry(**g), xt.astype(np.float64))
         bs.append(synth.add_noise(ax, synth.standard_normal(seed + 50 + i, ax.shape), "gaussian",
                                   0.01).astype(np.float32))
@@ -150,6 +154,28 @@ def test_batched_graph_equals_direct_calls():
     xe = host(run_batched(batch, b_arena, sched, eta))
     xg = host(run_batched(batch, b_arena, sched, eta, graph=True))
     np.testing.assert_array_equal(xe, xg)
+
+
+def test_batched_rectangular_slices():
+    """Slices wider than tall and taller than wide (64 x 40, 48 x 96, 80 x 18) in one batch: equal to
+    single-slice runs bitwise, and one slice against the oracle's loop."""
+    gds, batch, xts, bs, b_arena = make_batch(slices=[(64, 30), (48, 20), (80, 16)], seed=97,
+                                              heights=[40, 96, 18])
+    sched = schedule(3, 3, 3)
+    eta = etas(batch, gds)
+    say("batched rectangular")
+    xd = run_batched(batch, b_arena, sched, eta)
+    cfgs = [batch.get_config(k, 3 if k == 0 else 1) for k in range(len(FACTORS))]
+    for i, g in enumerate(gds):
+        ref = run_single(g, bs[i], sched, eta[:, i], cfgs)
+        np.testing.assert_array_equal(host(batch.image(xd, i)), ref)
+    og = oracle.Geometry(**gds[1])
+    so = [(FACTORS[k], None if n_sub <= 1 else synth.subset_views(sub, n_sub, gds[1]["n_views"]), sigma)
+          for k, n_sub, sub, sigma, _ in sched]
+    et = np.array([eta[k, 1] for k, *_ in sched], dtype=np.float64)
+    a = np.array([s[4] for s in sched])
+    ref = oracle.pnp_run(og, bs[1].astype(np.float64), so, et, a)
+    assert rel(host(batch.image(xd, 1)), ref) <= 1e-4, rel(host(batch.image(xd, 1)), ref)
 
 
 def test_batched_factor_not_dividing_the_tv_tile():
