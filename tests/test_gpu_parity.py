@@ -80,6 +80,9 @@ GEOMS = {
     # 0.15 pixel per bin at the isocentre: a 32-pixel block's footprint spans about 200 bins,
     # more than the back-projector stages per view at once (several chunks per view)
     "finepitch": dict(n=96, V=12, nb=640, det_pitch_mm=0.3),
+    # detector shifted by about half its width: many bins see no pixel (rays without samples
+    # next to the image edge, in every view)
+    "offset": dict(n=64, V=30, nb=64, det_offset_mm=60.0),
 }
 
 FP_CASES = [
@@ -91,6 +94,7 @@ FP_CASES = [
     ("diag", 1, None), ("diag", 2, None), ("tiny", 1, None), ("tiny", 2, ("list", [2])),
     ("widefan", 1, None), ("widefan", 2, None), ("widefan", 4, ("sub", 1, 4)),
     ("finepitch", 1, None), ("finepitch", 2, ("sub", 1, 3)),
+    ("offset", 1, None), ("offset", 2, None), ("offset", 4, ("sub", 2, 3)),
 ]
 
 
