@@ -300,7 +300,7 @@ def problem(name, seed=0):
 
 
 def run_gpu(plan, gd, b, sched, eta, a, alpha=1.0, lam=0.01, history=False, graph=False, chained=False,
-            events=None):
+            events=None, tv_iters=5):
     """Runs the schedule with pnp_step (or as one captured graph). sched: (stage_index, views, sigma).
     chained: direct calls with the graph's pooling hand-over; events: list that receives six
     timing events per step."""
@@ -319,7 +319,7 @@ def run_gpu(plan, gd, b, sched, eta, a, alpha=1.0, lam=0.01, history=False, grap
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
             events.append(ev)
         steps.append(fbpnp.pnp_args(plan, s, bd, yb, xb, xb, yb, float(eta[t]), float(a[t]), dv, sigma,
-                                    alpha, lam, 0.125, 5, None if hist is None else hist[t], ev))
+                                    alpha, lam, 0.125, tv_iters, None if hist is None else hist[t], ev))
     if chained:
         fbpnp.chain_steps(steps)
     if graph:
@@ -381,6 +381,25 @@ def test_pnp_step_large_odd_pooling_factors(form):
     say("pnp_step large factors, chained and graph", form)
     np.testing.assert_array_equal(run_gpu(plan, gd, b, sched_g, eta, a, chained=True), x)
     np.testing.assert_array_equal(run_gpu(plan, gd, b, sched_g, eta, a, graph=True), x)
+
+
+@pytest.mark.parametrize("lam,tv_iters,alpha", [(0.02, 8, 1.0), (0.01, 6, 0.7), (0.0, 5, 1.0), (0.01, 0, 0.8)])
+def test_pnp_step_denoiser_settings(lam, tv_iters, alpha):
+    """Fused steps with 6 to 8 TV steps (the deeper-halo denoiser), with lambda = 0 and with no TV
+    step (the denoiser kernel then only relaxes and applies the momentum), as direct calls and as
+    a graph (whose steps pool in the denoiser's epilogue)."""
+    w, gd, og, xt, b = problem("pnp64")
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [2, 1])
+    sched_g = [(0, None, 1.0)] * 3 + [(1, None, 1.0)] * 3
+    sched_o = [(2, None, 1.0)] * 3 + [(1, None, 1.0)] * 3
+    eta = np.full(6, 1.0 / oracle.power_lipschitz(og, 1, 40))
+    a = synth.momentum_table(6)
+    say("pnp_step denoiser", lam, tv_iters, alpha)
+    x = run_gpu(plan, gd, b, sched_g, eta, a, alpha=alpha, lam=lam, tv_iters=tv_iters)
+    ref = oracle.pnp_run(og, b.astype(np.float64), sched_o, eta, a, alpha=alpha, lam=lam, tv_iters=tv_iters)
+    assert rel(x, ref) <= 2e-5, rel(x, ref)
+    g = run_gpu(plan, gd, b, sched_g, eta, a, alpha=alpha, lam=lam, tv_iters=tv_iters, graph=True)
+    np.testing.assert_array_equal(g, x)
 
 
 def oracle_step(og, f):
