@@ -498,6 +498,24 @@ def main() -> int:
                 "conventional_gups": a_["pixel_views"] / sec / 1e9,
                 "gather_tb_per_s_effective": GATHER_BYTES_PER_SAMPLE * a_["samples"] / sec / 1e12}
                if name != "tv" else {}))
+    # each group's measured HBM rate (committed counter traffic per launch over the live
+    # launch time) and its share of the HBM roof; and the same for the timed kernels of a step
+    step_bytes, step_us, complete = 0, 0.0, True
+    for k, v in kernels.items():
+        t_k, _ = launch_traffic(k)
+        if t_k:
+            rate = t_k / (v["avg_launch_us"] * 1e-6) / 1e9
+            v.update(hbm_bytes_per_launch=t_k, hbm_gb_per_s=rate, hbm_frac=rate / PEAK_HBM_GBS)
+            step_bytes += t_k * v["launches_per_step"]
+            step_us += v["us_per_step"]
+        else:
+            complete = False
+    hbm_step = None
+    if complete and step_bytes:
+        hbm_step = {"bytes_per_step": step_bytes, "kernel_us_per_step": round(step_us, 2),
+                    "gb_per_s": round(step_bytes / (step_us * 1e-6) / 1e9, 1),
+                    "frac": round(step_bytes / (step_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 5),
+                    "covers": "the projector, back-projector and denoiser launches of a step"}
     for k, v in kernels.items():
         log(f"  {k}: {v}")
     dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["us_per_step"])
@@ -553,6 +571,7 @@ def main() -> int:
                                "1 of 8 view subsets, TV-prox 5 x lambda 0.01, FISTA momentum",
                    "iterations_per_step": T, "image": N, "views": V, "bins": B},
         "roofline": roofline,
+        "hbm_per_step": hbm_step,
         "launch_configs": configs,
         "cpu_baseline": cpu,
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
