@@ -30,7 +30,8 @@ if ROOT not in sys.path:
 # MI355X published figures used as roofline denominators
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
-# algorithmic FP32 operations per unit of work
+# algorithmic FP32 operations per unit of work (the arithmetic of the definitions, not the
+# instructions the kernels issue)
 FLOP_PER_FP_SAMPLE = 7      # position fma (2), fraction (1), interpolation sub+fma (3), accumulate (1)
 FLOP_PER_FP_RAY = 2         # length scaling and residual subtraction
 FLOP_PER_BP_SAMPLE = 8      # position fma (2), fraction (1), 1-w (1), two weighted fma (4)
