@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_fp_batch(const SliceDesc* __restrict__ 
                             b + D.sino_off, D.resid, nullptr);
 }
 
-template <int VG, int PX>
+template <int VG, int PX, bool kAllBins = false>
 __global__ __launch_bounds__(64 * VG) void k_bp_batch(const SliceDesc* __restrict__ desc,
                                                       const uint32_t* __restrict__ items, int stage, int view0,
                                                       int view_step, const float* __restrict__ eta, float sigma,
@@ -78,9 +78,9 @@ __global__ __launch_bounds__(64 * VG) void k_bp_batch(const SliceDesc* __restric
     const BatchStage& S = D.st[stage];
     const int n_sel = dcdiv(D.n_views, view_step);
     const float scale = eta[w.d - desc] * sigma / (float)(S.f * S.f);
-    dev::bp_body<VG, PX, true>(w.local, S.rays, S.vrec, D.n_bins, nullptr, view0, view_step, n_sel, D.n_views,
-                               D.resid, S.nxs, S.nys, dcdiv(S.nxs, 8 * PX), scale, nullptr, S.f, D.nx,
-                               y_prev + D.img_off, D.zbuf);
+    dev::bp_body<VG, PX, true, kAllBins>(w.local, S.rays, S.vrec, D.n_bins, nullptr, view0, view_step, n_sel,
+                                         D.n_views, D.resid, S.nxs, S.nys, dcdiv(S.nxs, 8 * PX), scale, nullptr, S.f,
+                                         D.nx, y_prev + D.img_off, D.zbuf);
 }
 
 template <int T, int H, int NT>
@@ -235,11 +235,27 @@ fb_status launch_fp_batch(fb_batch* B, int stage, int n_sub, int subset, const f
     return check_launch("batched fp");
 }
 
+// A slice whose back-projection blocks (8 px stage pixels) reach the source
+// circle: the whole batch's back-projection at that stage takes every bin of a
+// view as a candidate, with one pixel per lane.
+static bool batch_all_bins(const fb_batch* B, int stage, int px) {
+    for (const fb_plan* p : B->plans)
+        if (bp_blocks_reach_source(p->g, p->stages[stage], 8 * px)) return true;
+    return false;
+}
+
 fb_status launch_bp_batch(fb_batch* B, int stage, int n_sub, int subset, const float* eta, float sigma,
                           const float* y_prev, int px, int vg, hipStream_t s) {
+    const bool all_bins = batch_all_bins(B, stage, px);
+    if (all_bins) px = 1;
     const ItemTable* t;
     fb_status st = work_items(B, 2, stage, px, n_sub, s, &t);
     if (st != FB_OK) return st;
+    if (all_bins) {
+        FB_BLAUNCH((k_bp_batch<4, 1, true>), dim3(t->n), dim3(256), s, B->d_desc, t->d, stage, subset, n_sub, eta,
+                   sigma, y_prev);
+        return check_launch("batched bp");
+    }
 #define FB_BPB(VG, PX)                                                                                           \
     FB_BLAUNCH((k_bp_batch<VG, PX>), dim3(t->n), dim3(64 * VG), s, B->d_desc, t->d, stage, subset, n_sub, eta, sigma, \
                y_prev)
@@ -318,7 +334,8 @@ static fb_status warm_tables(fb_batch* B, const fb_batch_args* a) {
     fb_status st;
     if ((st = work_items(B, 0, a->stage, 0, 1, nullptr, &t)) != FB_OK) return st;
     if ((st = work_items(B, 1, a->stage, c.fp_seg, n_sub, nullptr, &t)) != FB_OK) return st;
-    if ((st = work_items(B, 2, a->stage, c.bp_px, n_sub, nullptr, &t)) != FB_OK) return st;
+    const int bp_px = batch_all_bins(B, a->stage, c.bp_px) ? 1 : c.bp_px;  // as launch_bp_batch chooses
+    if ((st = work_items(B, 2, a->stage, bp_px, n_sub, nullptr, &t)) != FB_OK) return st;
     return work_items(B, 3, 0, c.tv_tile, 1, nullptr, &t);
 }
 

@@ -144,10 +144,14 @@ __device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays
     }
     float acc = 0.f;
     if (L1 > L0) {
-        const int la = L0 + ((L1 - L0) * seg) / SEG, lb = L0 + ((L1 - L0) * (seg + 1)) / SEG;
+        // a wavefront can hold rays of both classes, whose lines run along different
+        // axes: each lane stops at the end of its own axis (beyond it the position of
+        // a ray is not kept out of the grid, and the reads would fall in the other image)
+        const int nlines = ymaj ? nys : nxs;
+        const int la = L0 + ((L1 - L0) * seg) / SEG, lb = min(L0 + ((L1 - L0) * (seg + 1)) / SEG, nlines);
         const int pitch = ymaj ? pitch_y : pitch_x;
         const int npos = ymaj ? nxs : nys;
-        const int mid = npos >> 1, lmid = (ymaj ? nys : nxs) >> 1;
+        const int mid = npos >> 1, lmid = nlines >> 1;
         const float plo = (float)(-2 - mid), phi = (float)(npos - mid);
         // byte offset of position mid on line la
         int off = ((ymaj ? ly_off : 0) + la * pitch + kPad + mid) * 4;
@@ -248,11 +252,13 @@ __device__ __forceinline__ void gather_strip(const float* __restrict__ st, int b
 // All strips of one dominance class for one staged view. The candidate bins
 // of a strip come from j(c, r) at its two ends (the numerator and the
 // denominator of j are linear in c and r); lo..hi is the class range within
-// the staged chunk.
-template <int PX, bool kXMajor>
+// the staged chunk. kAllBins: every ray of the class range is a candidate
+// (for stages whose pixel blocks, grown by the strip ends, reach the source
+// circle, where j of the block corners is no longer a valid projective value).
+template <int PX, bool kXMajor, bool kAllBins>
 __device__ __forceinline__ void bp_class(const ViewRec& vr, const float* __restrict__ st, int base, int lo,
-                                                   int hi, float cc, float rc, int c, int r, int mid_c, int mid_r,
-                                                   float (&acc)[PX][PX]) {
+                                         int hi, float cc, float rc, int c, int r, int mid_c, int mid_r,
+                                         float (&acc)[PX][PX]) {
     if (lo > hi) return;
     // x-major: strips are columns c+t over rows r-1 .. r+PX;
     // y-major: strips are rows r+t over columns c-1 .. c+PX
@@ -266,9 +272,10 @@ __device__ __forceinline__ void bp_class(const ViewRec& vr, const float* __restr
 #pragma unroll
     for (int t = 0; t < PX; ++t) {
         const float nt = fmaf(at, (float)t, n0), dt = fmaf(bt, (float)t, d0);
-        int jl, jh;
-        cand_range(fmaf(nt, __builtin_amdgcn_rcpf(dt), vr.j0), fmaf(nt + dn, __builtin_amdgcn_rcpf(dt + dd), vr.j0),
-                   lo, hi, jl, jh);
+        int jl = lo, jh = hi;
+        if constexpr (!kAllBins)
+            cand_range(fmaf(nt, __builtin_amdgcn_rcpf(dt), vr.j0),
+                       fmaf(nt + dn, __builtin_amdgcn_rcpf(dt + dd), vr.j0), lo, hi, jl, jh);
         float sacc[PX];
 #pragma unroll
         for (int w = 0; w < PX; ++w) sacc[w] = 0.f;
@@ -340,7 +347,10 @@ __device__ __forceinline__ void bp_finish(const float (*__restrict__ red)[PX * P
 // Work-group blk (64 VG threads) of a backprojection; views as in fp_body.
 // Fused form, optional extras: mu (a coarse gradient [nys][nxs]) enters the
 // step as z = y_prev - U(scale g + mu_scale mu); g_out receives g itself.
-template <int VG, int PX, bool kFused>
+// kAllBins: every bin of a view is staged and every ray of a class is a
+// candidate of every strip (launched for stages whose blocks reach the source
+// circle; see bp_class).
+template <int VG, int PX, bool kFused, bool kAllBins = false>
 __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays, const ViewRec* __restrict__ vrec,
                                         int n_bins, const int32_t* __restrict__ views, int view0, int view_step,
                                         int n_sel, int n_views, const float* __restrict__ y, int nxs, int nys,
@@ -378,14 +388,19 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
             const int iu = wave + VG * (t0 + lane);
             const int vu = views ? views[iu] : view0 + iu * view_step;
             if ((unsigned)vu < (unsigned)n_views) {  // invalid view index: no contribution
-                const ViewRec vq = vrec[vu];
-                const float q0 = proj_bin(vq, cb0, rb0), q1 = proj_bin(vq, cb1, rb0);
-                const float q2 = proj_bin(vq, cb0, rb1), q3 = proj_bin(vq, cb1, rb1);
-                const float jmin = fminf(fminf(q0, q1), fminf(q2, q3));
-                const float jmax = fmaxf(fmaxf(q0, q1), fmaxf(q2, q3));
                 my_v = vu;
-                my_j0 = (int)fmaxf(floorf(jmin - kProjEps), 0.f);
-                my_j1 = (int)fminf(ceilf(jmax + kProjEps), (float)(n_bins - 1));
+                if constexpr (kAllBins) {
+                    my_j0 = 0;
+                    my_j1 = n_bins - 1;
+                } else {
+                    const ViewRec vq = vrec[vu];
+                    const float q0 = proj_bin(vq, cb0, rb0), q1 = proj_bin(vq, cb1, rb0);
+                    const float q2 = proj_bin(vq, cb0, rb1), q3 = proj_bin(vq, cb1, rb1);
+                    const float jmin = fminf(fminf(q0, q1), fminf(q2, q3));
+                    const float jmax = fmaxf(fmaxf(q0, q1), fmaxf(q2, q3));
+                    my_j0 = (int)fmaxf(floorf(jmin - kProjEps), 0.f);
+                    my_j1 = (int)fminf(ceilf(jmax + kProjEps), (float)(n_bins - 1));
+                }
             }
         }
         const int tn = min(64, n_mine - t0);
@@ -412,9 +427,9 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (hasx) bp_class<PX, true>(vr, st, base, max(vr.xlo, base), min(vr.xhi, top), cc, rc, c, r, mid_c,
+                if (hasx) bp_class<PX, true, kAllBins>(vr, st, base, max(vr.xlo, base), min(vr.xhi, top), cc, rc, c, r, mid_c,
                                              mid_r, acc);
-                if (hasy) bp_class<PX, false>(vr, st, base, max(vr.ylo, base), min(vr.yhi, top), cc, rc, c, r, mid_c,
+                if (hasy) bp_class<PX, false, kAllBins>(vr, st, base, max(vr.ylo, base), min(vr.yhi, top), cc, rc, c, r, mid_c,
                                               mid_r, acc);
                 // the slot is rewritten only after every lane's reads
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

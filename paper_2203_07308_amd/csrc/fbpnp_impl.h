@@ -180,6 +180,11 @@ int default_fp_seg(long waves1);
 int default_bp_px(long npx);
 int default_bp_vg(int px, long nblk, int n_sel);
 int default_tv_tile(long tiles32);
+// True when the back-projector's pixel blocks of bw stage pixels, grown by the
+// strip ends, reach the source circle (within 0.1 %): there the detector
+// coordinate of a block corner is no projective value, and the back-projector
+// runs with every bin of a view a candidate.
+bool bp_blocks_reach_source(const fb_geom& g, const Stage& st, int bw);
 fb_status check_config(const fb_launch_config& c);
 fb_launch_config plan_config(const fb_plan* p, int stage, int n_sel);
 

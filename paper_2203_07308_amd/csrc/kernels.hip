@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_fp(const RayRec* __restrict__ rays, int
                               line_bytes, pitch_x, pitch_y, nxs, nys, b, y, proj_out);
 }
 
-template <int VG, int PX, bool kFused>
+template <int VG, int PX, bool kFused, bool kAllBins = false>
 __global__ __launch_bounds__(64 * VG) void k_bp(const RayRec* __restrict__ rays, const ViewRec* __restrict__ vrec,
                                                 int n_bins, const int32_t* __restrict__ views, int n_sel,
                                                 int n_views, const float* __restrict__ y, int nxs, int nys,
@@ -55,8 +55,8 @@ __global__ __launch_bounds__(64 * VG) void k_bp(const RayRec* __restrict__ rays,
                                                 const float* __restrict__ yprev, float* __restrict__ z,
                                                 const float* __restrict__ mu, float mu_scale,
                                                 float* __restrict__ g_out) {
-    dev::bp_body<VG, PX, kFused>(blockIdx.x, rays, vrec, n_bins, views, 0, 1, n_sel, n_views, y, nxs, nys, blocks_x,
-                                 scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
+    dev::bp_body<VG, PX, kFused, kAllBins>(blockIdx.x, rays, vrec, n_bins, views, 0, 1, n_sel, n_views, y, nxs, nys,
+                                           blocks_x, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
 }
 
 template <int T, int H, int NT>
@@ -209,6 +209,15 @@ int default_bp_vg(int px, long nblk, int n_sel) {
 }
 int default_tv_tile(long tiles32) { return tiles32 < 256 ? 16 : 32; }
 
+bool bp_blocks_reach_source(const fb_geom& g, const Stage& st, int bw) {
+    // the union of the blocks grown by one pixel on each side, in centred
+    // stage-pixel coordinates: its farthest corner from the isocentre
+    const double hx = 0.5 * (st.nxs - 1), hy = 0.5 * (st.nys - 1);
+    const double cx = std::max(hx + 1.0, cdiv(st.nxs, bw) * bw - hx);
+    const double cy = std::max(hy + 1.0, cdiv(st.nys, bw) * bw - hy);
+    return g.pixel_mm * st.f * std::hypot(cx, cy) >= (1.0 - 1e-3) * g.sod_mm;
+}
+
 fb_status check_config(const fb_launch_config& c) {
     auto in = [](int v, std::initializer_list<int> ok) {
         if (v == 0) return true;
@@ -271,10 +280,17 @@ static fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const 
                              const float* mu = nullptr, float mu_scale = 0.f, float* g_out = nullptr) {
     const Stage& st = p->stages[stage];
     const fb_launch_config c = plan_config(p, stage, n_sel);
-    const int px = c.bp_px, vg = c.bp_vg;
+    // blocks that reach the source circle: every bin a candidate, one pixel per lane
+    const bool all_bins = bp_blocks_reach_source(p->g, st, 8 * c.bp_px);
+    const int px = all_bins ? 1 : c.bp_px, vg = c.bp_vg;
     const int bw = 8 * px;
     const int bxs = cdiv(st.nxs, bw), bys = cdiv(st.nys, bw), nblk = bxs * bys;
     const int nb = p->g.n_bins, f = st.f, nx = p->g.nx;
+    if (all_bins) {
+        FB_LAUNCH((k_bp<4, 1, kFused, true>), dim3(nblk), dim3(256), s, st.rays, st.vrec, nb, views, n_sel,
+                  p->g.n_views, y, st.nxs, st.nys, bxs, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
+        return check_launch("fanbeam_bp");
+    }
 #define FB_BP(VG, PX)                                                                                         \
     FB_LAUNCH((k_bp<VG, PX, kFused>), dim3(nblk), dim3(64 * VG), s, st.rays, st.vrec, nb, views, n_sel,         \
               p->g.n_views, y, st.nxs, st.nys, bxs, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out)

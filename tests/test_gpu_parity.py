@@ -242,6 +242,74 @@ def test_degenerate_geometries_match_oracle(name):
     assert rel(x_g, x_o) <= 1e-5, rel(x_g, x_o)
 
 
+def random_geometry(seed):
+    """A seeded random valid geometry: grid up to 80 x 80 (often with a common factor), pixel 0.5 to
+    2 mm, source at 1.45 to 20 image circumradii, detector pitch and offset drawn with the fan kept
+    under 90 degrees, a random start angle, sometimes a limited angular range; and a pooling factor."""
+    rng = np.random.default_rng(seed)
+    nx, ny = int(rng.integers(1, 81)), int(rng.integers(1, 81))
+    if rng.random() < 0.5:
+        k = int(rng.choice([2, 3, 4, 8]))
+        nx, ny = max(k, nx - nx % k), max(k, ny - ny % k)
+    h = float(rng.uniform(0.5, 2.0))
+    radius = 0.5 * h * math.hypot(nx, ny)
+    sod = radius * float(rng.uniform(1.45, 20.0))
+    sdd = sod * float(rng.uniform(1.2, 3.0))
+    V, B = int(rng.integers(1, 41)), int(rng.integers(1, 121))
+    pitch = float(rng.uniform(0.2, 3.0)) * h * sdd / sod
+    off = float(rng.uniform(-0.3, 0.3)) * B * pitch
+    umax = 0.5 * (B - 1) * pitch + abs(off)
+    if umax >= 0.95 * sdd:
+        scale = 0.9 * sdd / umax
+        pitch, off = pitch * scale, off * scale
+    span = 2 * math.pi * (1.0 if rng.random() < 0.7 else float(rng.uniform(0.3, 1.0)))
+    gd = dict(nx=nx, ny=ny, pixel_mm=h, n_views=V, n_bins=B, sod_mm=sod, sdd_mm=sdd, det_pitch_mm=pitch,
+              det_offset_mm=off, angle0_rad=float(rng.uniform(0, 2 * math.pi)), angle_step_rad=span / V)
+    divs = [f for f in range(2, 9) if nx % f == 0 and ny % f == 0]
+    return gd, (int(rng.choice(divs)) if divs else 1)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_geometries_match_oracle(seed):
+    """Projection, back-projection in every launch shape, the adjoint identity, and three fused steps
+    captured as a graph, on a seeded random geometry, against the oracle."""
+    gd, f = random_geometry(seed)
+    og = oracle.Geometry(**gd)
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [f])
+    rng = np.random.default_rng(100 + seed)
+    nys, nxs = gd["ny"] // f, gd["nx"] // f
+    x = rng.random((nys, nxs)).astype(np.float32)
+    y = (0.5 + rng.random((gd["n_views"], gd["n_bins"]))).astype(np.float32)
+    say("random geometry", seed, gd["nx"], gd["ny"], gd["n_views"], gd["n_bins"], f)
+    ax = torch.empty(y.size, device="cuda")
+    fbpnp.fanbeam_fp(plan, 0, dev(x), ax)
+    got = host(ax).reshape(y.shape)
+    ref = oracle.fp(og, x.astype(np.float64), f)
+    for i in range(y.shape[0]):
+        if np.linalg.norm(ref[i]) > 0:
+            assert rel(got[i], ref[i]) <= 1e-5, (i, rel(got[i], ref[i]))
+        else:
+            assert np.all(got[i] == 0)
+    lhs = np.vdot(got.ravel().astype(np.float64), y.ravel().astype(np.float64))
+    refb = oracle.bp(og, y.astype(np.float64), f)
+    for form in BP_FORMS:
+        plan.set_config(0, form)
+        aty = torch.empty(x.size, device="cuda")
+        fbpnp.fanbeam_bp(plan, 0, dev(y), aty)
+        gb = host(aty)
+        assert rel(gb.reshape(refb.shape), refb) <= 1e-5, (form, rel(gb.reshape(refb.shape), refb))
+        rhs = np.vdot(x.ravel().astype(np.float64), gb.astype(np.float64))
+        assert abs(lhs - rhs) <= 1e-5 * abs(lhs), form
+    plan.set_config(0, None)
+    xt = rng.random((gd["ny"], gd["nx"]))
+    b = oracle.fp(og, xt).astype(np.float32)
+    eta = np.full(3, 1.0 / oracle.power_lipschitz(og, f, 40))
+    a = synth.momentum_table(3)
+    xg = run_gpu(plan, gd, b, [(0, None, 1.0)] * 3, eta, a, graph=True)
+    xo = oracle.pnp_run(og, b.astype(np.float64), [(f, None, 1.0)] * 3, eta, a)
+    assert rel(xg, xo) <= 2e-5, rel(xg, xo)
+
+
 @pytest.mark.parametrize("name", ["256", "widefan"])
 def test_stage_sample_counts_match_oracle(name):
     gd = make_geom(**GEOMS[name])
