@@ -204,6 +204,46 @@ def test_batched_factor_not_dividing_the_tv_tile():
     assert rel(got, ref) <= 1e-4, rel(got, ref)
 
 
+def test_batched_blocks_reaching_the_source():
+    """A slice with a coarse stage (f = 8, 9 x 4 stage pixels of 7.4 mm) and the source at 3 image
+    circumradii beside an ordinary slice: with 2 x 2 pixels per lane its back-projection blocks reach
+    the source circle, so the batch's back-projection at that stage takes every bin as a candidate.
+    Direct chained calls equal the graph; the close slice equals its single-slice run bit for bit (the
+    same every-bin variant), the other one to rounding (the batch ran it in that variant too); both
+    slices match the oracle."""
+    close = dict(nx=72, ny=32, pixel_mm=0.921235, n_views=28, n_bins=68, sod_mm=108.3165, sdd_mm=319.056,
+                 det_pitch_mm=5.43828, det_offset_mm=17.0564, angle0_rad=0.769074, angle_step_rad=0.224399)
+    gds = [close, synth.fan_geometry(64, 30)]
+    factors = [8, 1]
+    batch = fbpnp.Batch([fbpnp.Geometry(**g) for g in gds], factors)
+    batch.set_config(0, dict(fp_seg=0, bp_px=2, bp_vg=4, tv_tile=0))
+    bs = []
+    b_arena = torch.zeros(batch.sino_size, device="cuda")
+    for i, g in enumerate(gds):
+        xt = synth.rasterise(synth.random_ellipses(120 + i, 10, max(g["nx"], g["ny"])),
+                             max(g["nx"], g["ny"]))[:g["ny"], :g["nx"]].copy()
+        bs.append(oracle.fp(oracle.Geometry(**g), xt.astype(np.float64)).astype(np.float32))
+        batch.sinogram(b_arena, i).copy_(dev(bs[i]))
+    sched = schedule(3, 2, 2)
+    eta = etas(batch, gds, factors)
+    say("batched blocks reaching the source")
+    xd = run_batched(batch, b_arena, sched, eta)
+    np.testing.assert_array_equal(host(xd), host(run_batched(batch, b_arena, sched, eta, graph=True)))
+    cfgs = [batch.get_config(k, 2 if k == 0 else 1) for k in range(len(factors))]
+    for i, g in enumerate(gds):
+        single = run_single(g, bs[i], sched, eta[:, i], cfgs, factors=factors)
+        if i == 0:
+            np.testing.assert_array_equal(host(batch.image(xd, i)), single)
+        else:
+            assert rel(host(batch.image(xd, i)), single) <= 1e-6
+        so = [(factors[k], None if n_sub <= 1 else synth.subset_views(sub, n_sub, g["n_views"]), sigma)
+              for k, n_sub, sub, sigma, _ in sched]
+        et = np.array([eta[k, i] for k, *_ in sched], dtype=np.float64)
+        a = np.array([q[4] for q in sched])
+        ref = oracle.pnp_run(oracle.Geometry(**g), bs[i].astype(np.float64), so, et, a)
+        assert rel(host(batch.image(xd, i)), ref) <= 1e-4, (i, rel(host(batch.image(xd, i)), ref))
+
+
 def test_batched_slice_matches_oracle_loop():
     """Two slices of a batch against the FP64 oracle's sketched loop (relative L2 1e-4)."""
     gds, batch, xts, bs, b_arena = make_batch(slices=[(64, 90), (96, 47)], seed=70)
