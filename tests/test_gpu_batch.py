@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import oracle
+from random_geometry import random_geometry
 from paper_2203_07308_amd import fbpnp, synth
 
 pytestmark = pytest.mark.gpu
@@ -242,6 +243,44 @@ def test_batched_blocks_reaching_the_source():
         a = np.array([q[4] for q in sched])
         ref = oracle.pnp_run(oracle.Geometry(**g), bs[i].astype(np.float64), so, et, a)
         assert rel(host(batch.image(xd, i)), ref) <= 1e-4, (i, rel(host(batch.image(xd, i)), ref))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_batched_random_slices(seed):
+    """Three seeded random slices (sizes rounded down to a shared factor of 1 to 4, their own views,
+    bins, detectors and source distances) in one batch: the graph equals direct chained calls and
+    single-slice runs, and each slice matches the oracle's loop."""
+    rng = np.random.default_rng(700 + seed)
+    fc = int(rng.integers(1, 5))
+    gds = []
+    for k in range(3):
+        g, _ = random_geometry(1000 + 10 * seed + k)
+        g["nx"], g["ny"] = fc * max(1, g["nx"] // fc), fc * max(1, g["ny"] // fc)
+        gds.append(g)
+    factors = [fc, 1] if fc > 1 else [1]
+    batch = fbpnp.Batch([fbpnp.Geometry(**g) for g in gds], factors)
+    bs = []
+    b_arena = torch.zeros(batch.sino_size, device="cuda")
+    for i, g in enumerate(gds):
+        xt = rng.random((g["ny"], g["nx"]))
+        bs.append(oracle.fp(oracle.Geometry(**g), xt).astype(np.float32))
+        batch.sinogram(b_arena, i).copy_(dev(bs[i]))
+    T = 4
+    a_t = synth.momentum_table(T)
+    sched = [(0 if (len(factors) > 1 and t < 2) else len(factors) - 1, 1, 0, 1.0, float(a_t[t])) for t in range(T)]
+    eta = etas(batch, gds, factors)
+    say("batched random", seed, fc, [(g["nx"], g["ny"], g["n_views"], g["n_bins"]) for g in gds])
+    xd = run_batched(batch, b_arena, sched, eta)
+    np.testing.assert_array_equal(host(xd), host(run_batched(batch, b_arena, sched, eta, graph=True)))
+    cfgs = [batch.get_config(k, 1) for k in range(len(factors))]
+    for i, g in enumerate(gds):
+        got = host(batch.image(xd, i))
+        single = run_single(g, bs[i], sched, eta[:, i], cfgs, factors=factors)
+        assert rel(got, single) <= 1e-6, (i, rel(got, single))
+        so = [(factors[k], None, 1.0) for k, *_ in sched]
+        et = np.array([eta[k, i] for k, *_ in sched], dtype=np.float64)
+        ref = oracle.pnp_run(oracle.Geometry(**g), bs[i].astype(np.float64), so, et, np.asarray(a_t))
+        assert rel(got, ref) <= 1e-4, (i, rel(got, ref))
 
 
 def test_batched_slice_matches_oracle_loop():

@@ -8,6 +8,7 @@ import pytest
 import torch
 
 import oracle
+from random_geometry import random_geometry
 from paper_2203_07308_amd import fbpnp, synth
 
 pytestmark = pytest.mark.gpu
@@ -142,3 +143,32 @@ def test_bicubic_argument_checks():
         plan.set_sketch("lanczos")
     plan.set_sketch("pool")  # back to pooling: the step runs
     fbpnp.pnp_step(plan, fbpnp.pnp_args(plan, 0, b, x, x, x, torch.zeros_like(x), 1e-4, 0.0))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_bicubic_steps_on_random_geometries(seed):
+    """Three fused steps with the bicubic sketch, as a graph, on seeded random geometries with a
+    pooling factor (grids from a few to 80 pixels a side, close and far sources), against the oracle."""
+    g, f = random_geometry(40 + seed)
+    if f == 1:
+        f = 1 if g["nx"] % 2 or g["ny"] % 2 else 2
+    og = oracle.Geometry(**g)
+    plan = fbpnp.Plan(fbpnp.Geometry(**g), [f, 1] if f > 1 else [1])
+    plan.set_sketch("bicubic")
+    xt = np.random.default_rng(seed).random((g["ny"], g["nx"]))
+    b = oracle.fp(og, xt).astype(np.float32)
+    eta = np.full(3, 1.0 / oracle.power_lipschitz(og, f, 30, sketch="bicubic"))
+    a = synth.momentum_table(3)
+    say("bicubic random", seed, g["nx"], g["ny"], f)
+    npix = g["nx"] * g["ny"]
+    xb = torch.zeros(npix, device="cuda")
+    yb = torch.zeros(npix, device="cuda")
+    bd = dev(b).reshape(-1)
+    steps = [fbpnp.pnp_args(plan, 0, bd, yb, xb, xb, yb, float(eta[t]), float(a[t])) for t in range(3)]
+    gr = fbpnp.Graph(plan, steps)
+    gr.launch()
+    torch.cuda.synchronize()
+    gr.close()
+    got = host(xb).reshape(g["ny"], g["nx"])
+    ref = oracle.pnp_run(og, b.astype(np.float64), [(f, None, 1.0)] * 3, eta, a, sketch="bicubic")
+    assert rel(got, ref) <= 2e-5, rel(got, ref)
