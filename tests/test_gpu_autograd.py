@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import oracle
+from random_geometry import random_geometry
 from paper_2203_07308_amd import fbpnp, synth
 from paper_2203_07308_amd.autograd import StepSpec, unrolled_pnp
 
@@ -136,6 +137,37 @@ def test_unrolled_gradients_coarse_factor_three():
     g_x0, g_eta, r_x0, r_eta, *_ = run_case(gd, og, xts[0], bs[0], 4, 4, 5, x0, eta, fc=3)
     assert rel(g_x0, r_x0) <= 1e-3, rel(g_x0, r_x0)
     assert rel(g_eta, r_eta) <= 1e-3, (g_eta, r_eta)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_unrolled_gradients_on_random_geometries(seed):
+    """Gradients of 4 unrolled iterations (2 at the geometry's pooling factor, then 2 at f = 1, all
+    views) with respect to x0 and every step size, on seeded random geometries, against the oracle's
+    reverse pass."""
+    gd, f = random_geometry(80 + seed)
+    og = oracle.Geometry(**gd)
+    factors = [f, 1] if f > 1 else [1]
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), factors)
+    rng = np.random.default_rng(seed)
+    xt = rng.random((gd["ny"], gd["nx"]))
+    b = oracle.fp(og, xt).astype(np.float32)
+    T = 4
+    a = synth.momentum_table(T)
+    stages = [0, 0, len(factors) - 1, len(factors) - 1]
+    sched_o = [(factors[k], None, 1.0) for k in stages]
+    specs = [StepSpec(k, None, 1.0, float(a[t])) for t, k in enumerate(stages)]
+    eta = np.full(T, 0.5 / oracle.power_lipschitz(og, 1, 30))
+    x0 = 0.3 * xt
+    say("unrolled random", seed, gd["nx"], gd["ny"], f)
+    x0_t = dev(x0).requires_grad_(True)
+    eta_t = torch.tensor(eta, dtype=torch.float32, device="cuda", requires_grad=True)
+    xT = unrolled_pnp(plan, dev(b).reshape(-1), specs, x0_t, eta_t)
+    loss = 0.5 * ((xT - dev(xt)) ** 2).sum()
+    loss.backward()
+    r_x0, r_eta = oracle.pnp_vjp(og, b.astype(np.float64), sched_o, eta, a,
+                                 oracle.pnp_run(og, b.astype(np.float64), sched_o, eta, a, x0=x0) - xt, x0=x0)
+    assert rel(host(x0_t.grad), r_x0) <= 1e-3, rel(host(x0_t.grad), r_x0)
+    assert rel(host(eta_t.grad), r_eta) <= 1e-3, (host(eta_t.grad), r_eta)
 
 
 @pytest.mark.slow
