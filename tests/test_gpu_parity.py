@@ -278,11 +278,21 @@ def test_random_geometries_match_oracle(seed):
     plan.set_config(0, None)
     xt = rng.random((gd["ny"], gd["nx"]))
     b = oracle.fp(og, xt).astype(np.float32)
-    eta = np.full(3, 1.0 / oracle.power_lipschitz(og, f, 40))
+    eta = np.full(3, 1.0 / oracle.power_lipschitz(og, f, 30))
     a = synth.momentum_table(3)
     xg = run_gpu(plan, gd, b, [(0, None, 1.0)] * 3, eta, a, graph=True)
     xo = oracle.pnp_run(og, b.astype(np.float64), [(f, None, 1.0)] * 3, eta, a)
     assert rel(xg, xo) <= 2e-5, rel(xg, xo)
+    # the step size's power iteration (all views), and pooling and its adjoint at this factor
+    L = fbpnp.power_lipschitz(plan, 0, 30)
+    assert abs(L - 1.0 / eta[0]) <= 1e-4 * L, (L, 1.0 / eta[0])
+    xs = rng.random((gd["ny"], gd["nx"])).astype(np.float32)
+    v = torch.empty((nys, nxs), device="cuda")
+    fbpnp.sketch_down(dev(xs), f, v)
+    np.testing.assert_allclose(host(v), oracle.down(xs, f), rtol=1e-6, atol=1e-7)
+    up = torch.empty((gd["ny"], gd["nx"]), device="cuda")
+    fbpnp.sketch_up(dev(x), f, up)
+    np.testing.assert_allclose(host(up), oracle.up(x, f), rtol=1e-6, atol=1e-8)
 
 
 @pytest.mark.parametrize("name", ["256", "widefan"])
