@@ -8,6 +8,7 @@ import pytest
 import torch
 
 import oracle
+from random_geometry import random_geometry
 from paper_2203_07308_amd import fbpnp, synth
 
 pytestmark = pytest.mark.gpu
@@ -139,6 +140,27 @@ def test_svrg_two_stage_256_matches_oracle_and_graph():
     assert rel(got, ref) <= 1e-4, rel(got, ref)
     say("svrg graph")
     gg, _, _ = run(gd, b, stages, sched, eta, a, 4, graph=True)
+    np.testing.assert_array_equal(got, gg)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_svrg_on_random_geometries(seed):
+    """SVRG over 3 view subsets on seeded random geometries (a coarse stage when the grid allows one,
+    then f = 1; 6 iterations each), direct and as a graph, against the oracle."""
+    gd, f = random_geometry(200 + seed)
+    og = oracle.Geometry(**gd)
+    stages = [(f, 6), (1, 6)] if f > 1 else [(1, 6)]
+    n_sub = 3
+    sched = vr_schedule(stages, n_sub, 51 + seed)
+    L = {ff: oracle.power_lipschitz(og, ff, 30) for ff, _ in stages}
+    eta = np.array([0.5 / L[ff] for _, ff, _, _ in sched])
+    a = synth.momentum_table(len(sched))
+    b = oracle.fp(og, np.random.default_rng(seed).random((gd["ny"], gd["nx"]))).astype(np.float32)
+    say("svrg random", seed, gd["nx"], gd["ny"], gd["n_views"], f)
+    got, _, _ = run(gd, b, stages, sched, eta, a, n_sub)
+    ref = oracle_run(og, b, sched, eta, a, n_sub, gd["n_views"])
+    assert rel(got, ref) <= 1e-4, rel(got, ref)
+    gg, _, _ = run(gd, b, stages, sched, eta, a, n_sub, graph=True)
     np.testing.assert_array_equal(got, gg)
 
 
