@@ -575,10 +575,12 @@ __device__ __forceinline__ void tv_body(int bx, int by, const float* __restrict_
         __syncthreads();
     }
     float* const yst = su;  // free after the last step: holds y_t for the pooling epilogue
+    float yv[NP][2];        // y_t of the pair's two cells, for pooling straight from registers
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int e = e0[k];
         const size_t gi = ga[k];
+        yv[k][0] = yv[k][1] = 0.f;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (!(h == 0 ? out0[k] : out1[k])) continue;
@@ -602,10 +604,52 @@ __device__ __forceinline__ void tv_body(int bx, int by, const float* __restrict_
                 y_out[g] = yn;
                 if (hist) hist[g] = xr;
                 yst[e + h * S] = yn;
+                yv[k][h] = yn;
             }
         }
     }
-    if (pf > 0) {
+    if (pf == 1 || (pf == 2 && H % 2 == 0)) {
+        // pooling straight from registers, with no barrier: a pair is two rows of
+        // one column, and with an even halo the tile's pairs start on even rows and
+        // columns, so an f = 2 block is this pair and the next lane's (same sums,
+        // in the same order, as k_prepare)
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int q = threadIdx.x + k * NT;
+            const int pr = (live[k] ? q : NPAIR - 1) / S;
+            const int lc = (live[k] ? q : NPAIR - 1) - pr * S;
+            const int gr = R0 + 2 * pr, gc = C0 + lc;
+            if (pf == 1) {
+                if (H % 2 == 0 && out0[k] && out1[k]) {
+                    // the pair's rows are neighbours in the column image, 8-byte aligned
+                    // (even first row, even padding, line pitch a multiple of 4)
+                    *reinterpret_cast<float2*>(plx + (size_t)gc * ppx + kPad + gr) = make_float2(yv[k][0], yv[k][1]);
+                    ply[(size_t)gr * ppy + kPad + gc] = yv[k][0];
+                    ply[(size_t)(gr + 1) * ppy + kPad + gc] = yv[k][1];
+                } else {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if (!(h == 0 ? out0[k] : out1[k])) continue;
+                        plx[(size_t)gc * ppx + kPad + gr + h] = yv[k][h];
+                        ply[(size_t)(gr + h) * ppy + kPad + gc] = yv[k][h];
+                    }
+                }
+            } else {
+                const float ra = __shfl_xor(yv[k][0], 1), rb = __shfl_xor(yv[k][1], 1);
+                if (out0[k] && out1[k] && (lc & 1) == 0) {
+                    float sum = 0.f;
+                    sum += yv[k][0];
+                    sum += ra;
+                    sum += yv[k][1];
+                    sum += rb;
+                    sum *= pinv;
+                    const int R = gr >> 1, C = gc >> 1;
+                    plx[(size_t)C * ppx + kPad + R] = sum;
+                    ply[(size_t)R * ppy + kPad + C] = sum;
+                }
+            }
+        }
+    } else if (pf > 0) {
         // pooling of y_t for the next iteration's stage (pf x pf blocks inside
         // this tile), written into that stage's two line images with the same
         // arithmetic as k_prepare
