@@ -465,6 +465,21 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
 //   p_in/p_out: optional global dual field [2][ny][nx] for multi-launch runs
 //   (p_out set: the launch stores p for its tile instead of producing x).
 // ---------------------------------------------------------------------------
+// Sum of an F x F block of an LDS image with row pitch S, added from zero in
+// row order (k_prepare's order); all F^2 reads are issued before the sum.
+template <int F>
+__device__ __forceinline__ float pool_block(const float* __restrict__ b, int S) {
+    float v[F * F];
+#pragma unroll
+    for (int a = 0; a < F; ++a)
+#pragma unroll
+        for (int c = 0; c < F; ++c) v[a * F + c] = b[a * S + c];
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < F * F; ++k) s += v[k];
+    return s;
+}
+
 // Tile (bx, by) of the TV-prox, NT threads. Each thread owns vertical pairs
 // of cells (rows 2i, 2i+1 of one column of the haloed tile): their dual
 // values p1, p2 and z / lambda stay in registers, and LDS only carries what a
@@ -651,29 +666,29 @@ __device__ __forceinline__ void tv_body(int bx, int by, const float* __restrict_
         }
     } else if (pf > 0) {
         // pooling of y_t for the next iteration's stage (pf x pf blocks inside
-        // this tile), written into that stage's two line images with the same
-        // arithmetic as k_prepare
+        // this tile, pf >= 2 here), with the same arithmetic as k_prepare: one
+        // thread per block reads its values from LDS together, adds them in
+        // row order and stores the mean into both line images
         __syncthreads();
         const int tc = T / pf;
         const int Rc0 = (R0 + H) / pf, Cc0 = (C0 + H) / pf;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int e = threadIdx.x; e < tc * tc; e += NT) {
-                // consecutive threads walk the contiguous axis of the image written
-                const int u = e % tc, w = e / tc;
-                const int cr = pass == 0 ? u : w, cc = pass == 0 ? w : u;
-                const int R = Rc0 + cr, C = Cc0 + cc;
-                if (R >= pnys || C >= pnxs) continue;
-                float sum = 0.f;
-                if (pf == 1) {
-                    sum = yst[(H + cr) * S + H + cc];
-                } else {
-                    for (int a = 0; a < pf; ++a)
-                        for (int b = 0; b < pf; ++b) sum += yst[(H + cr * pf + a) * S + H + cc * pf + b];
-                    sum *= pinv;
-                }
-                if (pass == 0) plx[(size_t)C * ppx + kPad + R] = sum;
-                else ply[(size_t)R * ppy + kPad + C] = sum;
+        for (int e = threadIdx.x; e < tc * tc; e += NT) {
+            const int cr = e / tc, cc = e - cr * tc;
+            const int R = Rc0 + cr, C = Cc0 + cc;
+            if (R >= pnys || C >= pnxs) continue;
+            const float* const blk = yst + (H + cr * pf) * S + H + cc * pf;
+            float sum;
+            if (pf == 2) sum = pool_block<2>(blk, S);
+            else if (pf == 3) sum = pool_block<3>(blk, S);
+            else if (pf == 4) sum = pool_block<4>(blk, S);
+            else {
+                sum = 0.f;
+                for (int a = 0; a < pf; ++a)
+                    for (int b = 0; b < pf; ++b) sum += blk[a * S + b];
             }
+            sum *= pinv;
+            plx[(size_t)C * ppx + kPad + R] = sum;
+            ply[(size_t)R * ppy + kPad + C] = sum;
         }
     }
 }
