@@ -32,6 +32,21 @@ namespace dev {
 // ---------------------------------------------------------------------------
 constexpr int kTile = 32;
 
+// Sum of an F x F block of an image with row pitch S (global memory or LDS),
+// added from zero in row order; all F^2 reads are issued before the sum.
+template <int F>
+__device__ __forceinline__ float pool_block(const float* __restrict__ b, int S) {
+    float v[F * F];
+#pragma unroll
+    for (int a = 0; a < F; ++a)
+#pragma unroll
+        for (int c = 0; c < F; ++c) v[a * F + c] = b[a * S + c];
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < F * F; ++k) s += v[k];
+    return s;
+}
+
 // v = D_f x (x: ny x nx, full grid; f = 1 copies), written into both line images.
 __device__ __forceinline__ void prepare_body(int bx, int by, const float* __restrict__ x, int nx, int f,
                                              float inv_ff, int nxs, int nys, float* __restrict__ lx, int pitch_x,
@@ -46,10 +61,13 @@ __device__ __forceinline__ void prepare_body(int bx, int by, const float* __rest
             if (f == 1) {
                 s = x[(size_t)R * nx + C];
             } else {
-                for (int a = 0; a < f; ++a) {
-                    const float* row = x + (size_t)(f * R + a) * nx + (size_t)f * C;
-                    for (int b = 0; b < f; ++b) s += row[b];
-                }
+                const float* const blk = x + (size_t)(f * R) * nx + (size_t)f * C;
+                if (f == 2) s = pool_block<2>(blk, nx);
+                else if (f == 3) s = pool_block<3>(blk, nx);
+                else if (f == 4) s = pool_block<4>(blk, nx);
+                else
+                    for (int a = 0; a < f; ++a)
+                        for (int b = 0; b < f; ++b) s += blk[(size_t)a * nx + b];
                 s *= inv_ff;
             }
             ly[(size_t)R * pitch_y + kPad + C] = s;
@@ -465,21 +483,6 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
 //   p_in/p_out: optional global dual field [2][ny][nx] for multi-launch runs
 //   (p_out set: the launch stores p for its tile instead of producing x).
 // ---------------------------------------------------------------------------
-// Sum of an F x F block of an LDS image with row pitch S, added from zero in
-// row order (k_prepare's order); all F^2 reads are issued before the sum.
-template <int F>
-__device__ __forceinline__ float pool_block(const float* __restrict__ b, int S) {
-    float v[F * F];
-#pragma unroll
-    for (int a = 0; a < F; ++a)
-#pragma unroll
-        for (int c = 0; c < F; ++c) v[a * F + c] = b[a * S + c];
-    float s = 0.f;
-#pragma unroll
-    for (int k = 0; k < F * F; ++k) s += v[k];
-    return s;
-}
-
 // Tile (bx, by) of the TV-prox, NT threads. Each thread owns vertical pairs
 // of cells (rows 2i, 2i+1 of one column of the haloed tile): their dual
 // values p1, p2 and z / lambda stay in registers, and LDS only carries what a
