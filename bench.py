@@ -378,7 +378,6 @@ def main() -> int:
     L = {f: fbpnp.power_lipschitz(plan, stage_of[f], 100) for f in factors}
     eta = {f: 1.0 / L[f] for f in factors}
     n_sub = w.n_subsets
-    subsets = [torch.from_numpy(synth.subset_views(s, n_sub, V)).cuda() for s in range(n_sub)]
     log(f"setup {time.time() - t0:.1f}s  L={L}")
 
     x = torch.zeros(npix, device="cuda")
@@ -402,12 +401,13 @@ def main() -> int:
         steps = []
         for t, (f, s, a_t) in enumerate(sched):
             mode = 0 if vr is None else vr[t]
-            views = None if (s is None or mode == 1) else subsets[s]
-            sigma = 1.0 if views is None else float(n_sub)
+            # an interleaved subset goes by (k, n_sub): the kernels compute its view indices
+            sub = None if (s is None or mode == 1) else (s, n_sub)
+            sigma = 1.0 if sub is None else float(n_sub)
             sp, sg = (None, None) if mode == 0 else snaps[f]
-            steps.append(fbpnp.pnp_args(plan, stage_of[f], b, y, x, x, y, eta[f], a_t, views, sigma, w.alpha, w.lam,
+            steps.append(fbpnp.pnp_args(plan, stage_of[f], b, y, x, x, y, eta[f], a_t, None, sigma, w.alpha, w.lam,
                                         w.tau, w.tv_iters, None if hist is None else hist[t],
-                                        None if events is None else events[t], mode, sp, sg))
+                                        None if events is None else events[t], mode, sp, sg, subset=sub))
         return steps
 
     sk_sched = schedule(w.stages, 3000 * w.seed_base, n_sub)

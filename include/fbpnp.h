@@ -190,7 +190,13 @@ fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_
  *   x_t = (1 - alpha) z + alpha D(z)          (D: tv_prox with lambda, tau, tv_iters <= 8)
  *   y_t = x_t + a_t (x_t - x_{t-1})
  * b is the full sinogram [n_views][n_bins]; views/n_sel select M as in
- * fanbeam_fp. y_out may equal y_prev and x_out may equal x_prev (in-place
+ * fanbeam_fp, or, with views NULL, n_sub > 1 selects the interleaved subset
+ * subset, subset + n_sub, subset + 2 n_sub, ... (Algorithm 1, Option 2):
+ * 0 <= subset < n_sub, and n_sel must equal its size,
+ * ceil((n_views - subset) / n_sub). The kernels then compute each view index
+ * instead of reading it from a list. n_sub = 0 (or 1) and subset = 0 leave
+ * the selection to views/n_sel; giving both a list and n_sub > 1 is
+ * FB_EINVAL. y_out may equal y_prev and x_out may equal x_prev (in-place
  * iteration). history, if not NULL, receives a copy of x_t.
  * Chaining (optional, set automatically by fb_graph_create): next_stage >= 0
  * makes this call also pool y_t for stage next_stage into the plan workspace;
@@ -234,6 +240,7 @@ typedef struct fb_pnp_args {
     int32_t vr_mode;
     float* snap_proj;
     float* snap_grad;
+    int32_t n_sub, subset;
 } fb_pnp_args;
 fb_status pnp_step(const fb_plan* plan, const fb_pnp_args* args, hipStream_t stream);
 

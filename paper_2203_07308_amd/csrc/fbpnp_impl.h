@@ -131,6 +131,18 @@ struct TimedLaunch {  // scoped: events ev[i], ev[i + 1] (ev may be NULL)
 fb_status check_stage(const fb_plan* p, int stage);
 fb_status check_views(const fb_plan* p, const int32_t* views, int n_sel);
 
+// A selection of n views: list[i] (device) when list is not NULL, else
+// view0 + step i.
+struct ViewSel {
+    const int32_t* list;
+    int n;
+    int view0 = 0, step = 1;
+};
+// The selection of a pnp_step (a list, an interleaved subset or every view),
+// and its validation.
+ViewSel pnp_views(const fb_pnp_args* a);
+fb_status check_pnp_views(const fb_plan* p, const fb_pnp_args* a);
+
 struct StageLines {
     float* lx;   // x-major line image [nxs][pitch_x]
     float* ly;   // y-major line image [nys][pitch_y], directly after lx
@@ -143,11 +155,11 @@ StageLines stage_lines(const fb_plan* p, int stage);
 fb_status launch_prepare(const fb_plan* p, int stage, const float* x, int nx, int f, hipStream_t s);
 // Projection of the selected views from the stage's line images (minus b when resid).
 // proj_out (optional): the raw projection by view, [n_views][n_bins].
-fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* views, int n_sel, const float* b,
-                    float* y, hipStream_t s, float* proj_out = nullptr);
+fb_status launch_fp(const fb_plan* p, int stage, bool resid, const ViewSel& sel, const float* b, float* y,
+                    hipStream_t s, float* proj_out = nullptr);
 // Backprojection: xo = scale A_s^T y (coarse), or fused: z = yprev - scale D^T-replicate(A_s^T y).
-fb_status launch_bp(const fb_plan* p, int stage, const float* y, const int32_t* views, int n_sel, float scale,
-                    float* xo, const float* yprev, float* z, bool fused, hipStream_t s);
+fb_status launch_bp(const fb_plan* p, int stage, const float* y, const ViewSel& sel, float scale, float* xo,
+                    const float* yprev, float* z, bool fused, hipStream_t s);
 
 // Pooling target for the TV epilogue: the line images of the next stage.
 struct PoolTarget {

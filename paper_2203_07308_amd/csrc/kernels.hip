@@ -38,24 +38,27 @@ __global__ __launch_bounds__(256) void k_prepare(const float* __restrict__ x, in
 
 template <bool kResid, int SEG>
 __global__ __launch_bounds__(256) void k_fp(const RayRec* __restrict__ rays, int n_bins, int bins_padded,
-                                            const int32_t* __restrict__ views, int n_sel, int n_views,
+                                            const int32_t* __restrict__ views, int view0, int view_step, int n_sel,
+                                            int n_views,
                                             const float* __restrict__ lines, int ly_off, int line_bytes,
                                             int pitch_x, int pitch_y, int nxs, int nys,
                                             const float* __restrict__ b, float* __restrict__ y,
                                             float* __restrict__ proj_out) {
-    dev::fp_body<kResid, SEG>(blockIdx.x, rays, n_bins, bins_padded, views, 0, 1, n_sel, n_views, lines, ly_off,
-                              line_bytes, pitch_x, pitch_y, nxs, nys, b, y, proj_out);
+    dev::fp_body<kResid, SEG>(blockIdx.x, rays, n_bins, bins_padded, views, view0, view_step, n_sel, n_views, lines,
+                              ly_off, line_bytes, pitch_x, pitch_y, nxs, nys, b, y, proj_out);
 }
 
 template <int VG, int PX, bool kFused, bool kAllBins = false>
 __global__ __launch_bounds__(64 * VG) void k_bp(const RayRec* __restrict__ rays, const ViewRec* __restrict__ vrec,
-                                                int n_bins, const int32_t* __restrict__ views, int n_sel,
+                                                int n_bins, const int32_t* __restrict__ views, int view0,
+                                                int view_step, int n_sel,
                                                 int n_views, const float* __restrict__ y, int nxs, int nys,
                                                 int blocks_x, float scale, float* __restrict__ xo, int f, int nx,
                                                 const float* __restrict__ yprev, float* __restrict__ z,
                                                 const float* __restrict__ mu, float mu_scale,
                                                 float* __restrict__ g_out) {
-    dev::bp_body<VG, PX, kFused, kAllBins>(blockIdx.x, rays, vrec, n_bins, views, 0, 1, n_sel, n_views, y, nxs, nys,
+    dev::bp_body<VG, PX, kFused, kAllBins>(blockIdx.x, rays, vrec, n_bins, views, view0, view_step, n_sel, n_views, y,
+                                           nxs, nys,
                                            blocks_x, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
 }
 
@@ -172,6 +175,25 @@ fb_status check_views(const fb_plan* p, const int32_t* views, int n_sel) {
     return FB_OK;
 }
 
+ViewSel pnp_views(const fb_pnp_args* a) {
+    if (!a->views && a->n_sub > 1) return ViewSel{nullptr, a->n_sel, a->subset, a->n_sub};
+    return ViewSel{a->views, a->n_sel};
+}
+
+fb_status check_pnp_views(const fb_plan* p, const fb_pnp_args* a) {
+    if (a->n_sub > 1 || a->subset != 0) {
+        if (a->views) return fail(FB_EINVAL, "pnp_step: give a view list or (n_sub, subset), not both");
+        if (a->n_sub < 1 || a->subset < 0 || a->subset >= a->n_sub)
+            return fail(FB_EINVAL, "pnp_step: need 0 <= subset < n_sub");
+        const int count = (p->g.n_views - a->subset + a->n_sub - 1) / a->n_sub;
+        if (count < 1) return fail(FB_EINVAL, "pnp_step: the subset holds no view");
+        if (a->n_sel != count) return fail(FB_EINVAL, "pnp_step: n_sel must equal the number of views in the subset");
+        return FB_OK;
+    }
+    if (a->n_sub < 0) return fail(FB_EINVAL, "pnp_step: n_sub must not be negative");
+    return check_views(p, a->views, a->n_sel);
+}
+
 // Line images of a stage live in one plan allocation, one region per stage.
 StageLines stage_lines(const fb_plan* p, int stage) {
     size_t off = 0;
@@ -247,8 +269,9 @@ fb_launch_config plan_config(const fb_plan* p, int stage, int n_sel) {
     return c;
 }
 
-fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* views, int n_sel, const float* b,
-                    float* y, hipStream_t s, float* proj_out) {
+fb_status launch_fp(const fb_plan* p, int stage, bool resid, const ViewSel& sel, const float* b, float* y,
+                    hipStream_t s, float* proj_out) {
+    const int n_sel = sel.n;
     const Stage& st = p->stages[stage];
     StageLines L = stage_lines(p, stage);
     const int nb = p->g.n_bins;
@@ -257,7 +280,8 @@ fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* view
     const int bp = cdiv(nb, rays_per_wave) * rays_per_wave;
     const int blocks = cdiv(n_sel * (bp / rays_per_wave), 4);
 #define FB_FP(RES, SG)                                                                                        \
-    FB_LAUNCH((k_fp<RES, SG>), dim3(blocks), dim3(256), s, st.rays, nb, bp, views, n_sel, p->g.n_views, L.lx,   \
+    FB_LAUNCH((k_fp<RES, SG>), dim3(blocks), dim3(256), s, st.rays, nb, bp, sel.list, sel.view0, sel.step,      \
+              n_sel, p->g.n_views, L.lx,                                                                      \
               L.ly_off, L.bytes, st.pitch_x, st.pitch_y, st.nxs, st.nys, b, y, proj_out)
     if (resid) {
         if (seg == 8) FB_FP(true, 8);
@@ -275,10 +299,10 @@ fb_status launch_fp(const fb_plan* p, int stage, bool resid, const int32_t* view
 }
 
 template <bool kFused>
-static fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const int32_t* views, int n_sel,
-                             float scale, float* xo, const float* yprev, float* z, hipStream_t s,
+static fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const ViewSel& sel, float scale, float* xo, const float* yprev, float* z, hipStream_t s,
                              const float* mu = nullptr, float mu_scale = 0.f, float* g_out = nullptr) {
     const Stage& st = p->stages[stage];
+    const int n_sel = sel.n;
     const fb_launch_config c = plan_config(p, stage, n_sel);
     // blocks that reach the source circle: every bin a candidate, one pixel per lane
     const bool all_bins = bp_blocks_reach_source(p->g, st, 8 * c.bp_px);
@@ -287,12 +311,12 @@ static fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const 
     const int bxs = cdiv(st.nxs, bw), bys = cdiv(st.nys, bw), nblk = bxs * bys;
     const int nb = p->g.n_bins, f = st.f, nx = p->g.nx;
     if (all_bins) {
-        FB_LAUNCH((k_bp<4, 1, kFused, true>), dim3(nblk), dim3(256), s, st.rays, st.vrec, nb, views, n_sel,
+        FB_LAUNCH((k_bp<4, 1, kFused, true>), dim3(nblk), dim3(256), s, st.rays, st.vrec, nb, sel.list, sel.view0, sel.step, n_sel,
                   p->g.n_views, y, st.nxs, st.nys, bxs, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
         return check_launch("fanbeam_bp");
     }
 #define FB_BP(VG, PX)                                                                                         \
-    FB_LAUNCH((k_bp<VG, PX, kFused>), dim3(nblk), dim3(64 * VG), s, st.rays, st.vrec, nb, views, n_sel,         \
+    FB_LAUNCH((k_bp<VG, PX, kFused>), dim3(nblk), dim3(64 * VG), s, st.rays, st.vrec, nb, sel.list, sel.view0, sel.step, n_sel,         \
               p->g.n_views, y, st.nxs, st.nys, bxs, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out)
 #define FB_BP_VG(PX)           \
     switch (vg) {              \
@@ -318,10 +342,10 @@ static fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const 
     return check_launch("fanbeam_bp");
 }
 
-fb_status launch_bp(const fb_plan* p, int stage, const float* y, const int32_t* views, int n_sel, float scale,
-                    float* xo, const float* yprev, float* z, bool fused, hipStream_t s) {
-    return fused ? launch_bp_t<true>(p, stage, y, views, n_sel, scale, xo, yprev, z, s)
-                 : launch_bp_t<false>(p, stage, y, views, n_sel, scale, xo, yprev, z, s);
+fb_status launch_bp(const fb_plan* p, int stage, const float* y, const ViewSel& sel, float scale, float* xo,
+                    const float* yprev, float* z, bool fused, hipStream_t s) {
+    return fused ? launch_bp_t<true>(p, stage, y, sel, scale, xo, yprev, z, s)
+                 : launch_bp_t<false>(p, stage, y, sel, scale, xo, yprev, z, s);
 }
 
 fb_status capture_graph(const std::function<fb_status(hipStream_t)>& body, fb_graph** out) {
@@ -499,7 +523,7 @@ fb_status fanbeam_fp(const fb_plan* p, int stage, const float* x, float* y, cons
     if ((st = check_views(p, views, n_sel)) != FB_OK) return st;
     const Stage& S = p->stages[stage];
     if ((st = launch_prepare(p, stage, x, S.nxs, 1, stream)) != FB_OK) return st;
-    return launch_fp(p, stage, false, views, n_sel, nullptr, y, stream);
+    return launch_fp(p, stage, false, ViewSel{views, n_sel}, nullptr, y, stream);
 }
 
 fb_status fanbeam_bp(const fb_plan* p, int stage, const float* y, float* x, const int32_t* views, int n_sel,
@@ -508,7 +532,7 @@ fb_status fanbeam_bp(const fb_plan* p, int stage, const float* y, float* x, cons
     if (st != FB_OK) return st;
     if (!x || !y) return fail(FB_EINVAL, "fanbeam_bp: x and y must not be NULL");
     if ((st = check_views(p, views, n_sel)) != FB_OK) return st;
-    return launch_bp_t<false>(p, stage, y, views, n_sel, scale, x, nullptr, nullptr, stream);
+    return launch_bp_t<false>(p, stage, y, ViewSel{views, n_sel}, scale, x, nullptr, nullptr, stream);
 }
 
 fb_status sketch_down(const float* x, int nx, int ny, int f, float* v, hipStream_t stream) {
@@ -612,11 +636,11 @@ static fb_status pnp_step_bicubic(const fb_plan* p, const fb_pnp_args* a, hipStr
     if ((st = launch_bicubic_down(p, a->stage, a->y_prev, nullptr, stream)) != FB_OK) return st;
     {
         TimedLaunch tl(a->events, 0);
-        if ((st = launch_fp(p, a->stage, true, a->views, a->n_sel, a->b, p->resid, stream)) != FB_OK) return st;
+        if ((st = launch_fp(p, a->stage, true, pnp_views(a), a->b, p->resid, stream)) != FB_OK) return st;
     }
     {
         TimedLaunch tl(a->events, 2);
-        if ((st = launch_bp_t<false>(p, a->stage, p->resid, a->views, a->n_sel, 1.f, p->sk_g, nullptr, nullptr,
+        if ((st = launch_bp_t<false>(p, a->stage, p->resid, pnp_views(a), 1.f, p->sk_g, nullptr, nullptr,
                                      stream)) != FB_OK)
             return st;
     }
@@ -629,7 +653,7 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
     if (!a) return fail(FB_EINVAL, "pnp_step: args is NULL");
     fb_status st = check_stage(p, a->stage);
     if (st != FB_OK) return st;
-    if ((st = check_views(p, a->views, a->n_sel)) != FB_OK) return st;
+    if ((st = check_pnp_views(p, a)) != FB_OK) return st;
     if (!a->b || !a->y_prev || !a->x_prev || !a->x_out || !a->y_out)
         return fail(FB_EINVAL, "pnp_step: null buffer");
     if (a->tv_iters < 0 || a->tv_iters > kTvMaxFused) return fail(FB_EINVAL, "pnp_step: tv_iters must be in [0, 8]");
@@ -650,14 +674,14 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
     const bool snap = a->vr_mode == 1, vr = a->vr_mode == 2;
     {
         TimedLaunch tl(a->events, 0);
-        if ((st = launch_fp(p, a->stage, true, a->views, a->n_sel, vr ? a->snap_proj : a->b, p->resid, stream,
+        if ((st = launch_fp(p, a->stage, true, pnp_views(a), vr ? a->snap_proj : a->b, p->resid, stream,
                             snap ? a->snap_proj : nullptr)) != FB_OK)
             return st;
     }
     const float step = a->eta * a->sigma / (float)(S.f * S.f);
     {
         TimedLaunch tl(a->events, 2);
-        if ((st = launch_bp_t<true>(p, a->stage, p->resid, a->views, a->n_sel, step, nullptr, a->y_prev, p->zbuf,
+        if ((st = launch_bp_t<true>(p, a->stage, p->resid, pnp_views(a), step, nullptr, a->y_prev, p->zbuf,
                                     stream, vr ? a->snap_grad : nullptr, a->eta / (float)(S.f * S.f),
                                     snap ? a->snap_grad : nullptr)) != FB_OK)
             return st;
@@ -726,9 +750,9 @@ fb_status fb_power_lipschitz(const fb_plan* p, int stage, int n_iter, double* ou
     for (int it = 0; it <= n_iter; ++it) {
         st = bic ? launch_bicubic_down(p, stage, v, nullptr, stream) : launch_prepare(p, stage, v, nx, S.f, stream);
         if (st != FB_OK) return st;
-        if ((st = launch_fp(p, stage, false, nullptr, nv, nullptr, p->resid, stream)) != FB_OK) return st;
+        if ((st = launch_fp(p, stage, false, ViewSel{nullptr, nv}, nullptr, p->resid, stream)) != FB_OK) return st;
         if (it == n_iter) break;
-        if ((st = launch_bp_t<false>(p, stage, p->resid, nullptr, nv, 1.f, gs, nullptr, nullptr, stream)) != FB_OK)
+        if ((st = launch_bp_t<false>(p, stage, p->resid, ViewSel{nullptr, nv}, 1.f, gs, nullptr, nullptr, stream)) != FB_OK)
             return st;
         if (bic) {
             if ((st = launch_bicubic_up(p, stage, gs, 1.f, nullptr, w, stream)) != FB_OK) return st;

@@ -267,7 +267,7 @@ static fb_status autotune_plan(fb_plan* p, int n_sel, const char* cache_path, hi
             segs,
             [&](const int& c) {
                 p->cfg[k].fp_seg = c;
-                return launch_fp(p, k, true, vp, n_sel, b.f(), proj.f(), s);
+                return launch_fp(p, k, true, ViewSel{vp, n_sel}, b.f(), proj.f(), s);
             },
             [&](std::vector<float>& h) { return download(h, proj.f(), nproj); }, s, &seg);
         if (st != FB_OK) return st;
@@ -282,10 +282,10 @@ static fb_status autotune_plan(fb_plan* p, int n_sel, const char* cache_path, hi
             [&](const std::pair<int, int>& c) {
                 p->cfg[k].bp_px = c.first;
                 p->cfg[k].bp_vg = c.second;
-                return launch_bp(p, k, sino.f(), vp, n_sel, 1e-3f, nullptr, yprev.f(), p->zbuf, true, s);
+                return launch_bp(p, k, sino.f(), ViewSel{vp, n_sel}, 1e-3f, nullptr, yprev.f(), p->zbuf, true, s);
             },
             [&](std::vector<float>& h) {
-                fb_status r = launch_bp(p, k, sino.f(), vp, n_sel, 1.f, out.f(), nullptr, nullptr, false, s);
+                fb_status r = launch_bp(p, k, sino.f(), ViewSel{vp, n_sel}, 1.f, out.f(), nullptr, nullptr, false, s);
                 if (r == FB_OK && hipStreamSynchronize(s) != hipSuccess) r = fail(FB_EHIP, "autotune: sync");
                 return r == FB_OK ? download(h, out.f(), ncoarse) : r;
             },

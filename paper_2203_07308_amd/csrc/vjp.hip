@@ -240,7 +240,7 @@ fb_status pnp_step_vjp(const fb_plan* p, const fb_pnp_args* a, const float* xbar
     if (!a || !xbar || !ybar_prev || !eta_bar) return fail(FB_EINVAL, "pnp_step_vjp: null argument");
     fb_status st = check_stage(p, a->stage);
     if (st != FB_OK) return st;
-    if ((st = check_views(p, a->views, a->n_sel)) != FB_OK) return st;
+    if ((st = check_pnp_views(p, a)) != FB_OK) return st;
     if (!a->b || !a->y_prev) return fail(FB_EINVAL, "pnp_step_vjp: null buffer in args");
     if (a->vr_mode != 0) return fail(FB_EINVAL, "pnp_step_vjp: variance-reduced steps are not differentiated");
     if (bicubic_stage(p, a->stage)) return fail(FB_EINVAL, "pnp_step_vjp: differentiated with the pooling sketch only");
@@ -266,8 +266,8 @@ fb_status pnp_step_vjp(const fb_plan* p, const fb_pnp_args* a, const float* xbar
     const dim3 grid(cdiv(nx, 256), ny);
     // forward recomputation: gs = sigma A_s^T M (M A_s S y - M b), z = y - eta U gs
     if ((st = launch_prepare(p, a->stage, a->y_prev, nx, f, stream)) != FB_OK) return st;
-    if ((st = launch_fp(p, a->stage, true, a->views, a->n_sel, a->b, p->resid, stream)) != FB_OK) return st;
-    if ((st = launch_bp(p, a->stage, p->resid, a->views, a->n_sel, a->sigma, gs, nullptr, nullptr, false, stream)) !=
+    if ((st = launch_fp(p, a->stage, true, pnp_views(a), a->b, p->resid, stream)) != FB_OK) return st;
+    if ((st = launch_bp(p, a->stage, p->resid, pnp_views(a), a->sigma, gs, nullptr, nullptr, false, stream)) !=
         FB_OK)
         return st;
     const float inv_ff = 1.f / (float)(f * f);
@@ -283,8 +283,8 @@ fb_status pnp_step_vjp(const fb_plan* p, const fb_pnp_args* a, const float* xbar
     if ((st = check_launch("pnp_step_vjp eta")) != FB_OK) return st;
     // ybar_prev = zbar - eta sigma U A_s^T M^T M A_s S zbar
     if ((st = launch_prepare(p, a->stage, zbar, nx, f, stream)) != FB_OK) return st;
-    if ((st = launch_fp(p, a->stage, false, a->views, a->n_sel, nullptr, p->resid, stream)) != FB_OK) return st;
-    if ((st = launch_bp(p, a->stage, p->resid, a->views, a->n_sel, a->eta * a->sigma * inv_ff, nullptr, zbar, ybar_prev,
+    if ((st = launch_fp(p, a->stage, false, pnp_views(a), nullptr, p->resid, stream)) != FB_OK) return st;
+    if ((st = launch_bp(p, a->stage, p->resid, pnp_views(a), a->eta * a->sigma * inv_ff, nullptr, zbar, ybar_prev,
                         true, stream)) != FB_OK)
         return st;
     if (combine && ybar) {

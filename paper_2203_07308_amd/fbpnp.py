@@ -63,6 +63,7 @@ class PnpArgs(ctypes.Structure):
         ("next_stage", ctypes.c_int32), ("prepared", ctypes.c_int32),
         ("events", ctypes.POINTER(ctypes.c_void_p)),
         ("vr_mode", ctypes.c_int32), ("snap_proj", ctypes.c_void_p), ("snap_grad", ctypes.c_void_p),
+        ("n_sub", ctypes.c_int32), ("subset", ctypes.c_int32),
     ]
 
 
@@ -328,18 +329,26 @@ def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float
              views: torch.Tensor | None = None, sigma: float = 1.0, alpha: float = 1.0, lam: float = 0.01,
              tau: float = 0.125, tv_iters: int = 5, history: torch.Tensor | None = None,
              events=None, vr_mode: int = 0, snap_proj: torch.Tensor | None = None,
-             snap_grad: torch.Tensor | None = None) -> PnpArgs:
+             snap_grad: torch.Tensor | None = None, subset: tuple[int, int] | None = None) -> PnpArgs:
     """Arguments of one pnp_step. events: optional sequence of six torch.cuda.Event
     (enable_timing=True) or None, recorded around the step's fp, bp and TV kernels.
     vr_mode 1 / 2 with snap_proj [n_views * n_bins] and snap_grad (the stage's coarse
-    image size): variance-reduced snapshot / step (see include/fbpnp.h)."""
+    image size): variance-reduced snapshot / step (see include/fbpnp.h).
+    subset = (k, n_sub), with views None: the interleaved subset k, k + n_sub, ...
+    of the views, whose indices the kernels compute instead of reading a list."""
     npix = plan.geom.nx * plan.geom.ny
+    if subset is not None and views is not None:
+        raise ValueError("pnp_args: give views or subset, not both")
     vp, n_sel = _views(plan, views)
+    k_sub, n_sub = (0, 0) if subset is None else (int(subset[0]), int(subset[1]))
+    if subset is not None:
+        n_sel = len(range(k_sub, plan.geom.n_views, max(n_sub, 1)))
     a = PnpArgs(stage, vp, n_sel, sigma, eta, alpha, a_t, lam, tau, tv_iters,
                 _ptr(b, numel=plan.geom.n_views * plan.geom.n_bins, name="b"),
                 _ptr(y_prev, numel=npix, name="y_prev"), _ptr(x_prev, numel=npix, name="x_prev"),
                 _ptr(x_out, numel=npix, name="x_out"), _ptr(y_out, numel=npix, name="y_out"),
                 _ptr(history, numel=npix, name="history"), -1, 0)
+    a.n_sub, a.subset = n_sub, k_sub
     if vr_mode:
         nys, nxs = plan.coarse_shape(stage)
         a.vr_mode = vr_mode
