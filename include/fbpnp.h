@@ -220,6 +220,9 @@ fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_
  *      g_M(y) - g_M(y_snap) + g(y_snap) with the last snapshot of this stage.
  * A snapshot's buffers belong to one stage; take a new snapshot when the stage
  * changes.
+ * Every optional field (history, events, vr_mode and its buffers, n_sub,
+ * subset) means "not used" at zero: zero-initialise the struct
+ * (fb_pnp_args a = {0}) and set the fields in use.
  */
 typedef struct fb_pnp_args {
     int32_t stage;
