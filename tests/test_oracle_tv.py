@@ -115,3 +115,64 @@ def test_five_steps_reduce_the_rof_objective():
     ref = rof_projected_gradient(z, lam)
     assert P(ref) < P(x5) < P(z)
     assert np.linalg.norm(x5 - ref) < np.linalg.norm(z - ref)
+
+
+def _golden_tv_cases():
+    """Rows of tests/golden/tv_prox_chambolle_small.txt: (name, z, n_iter, x) with x exact."""
+    import os
+    import re
+    from fractions import Fraction
+
+    def value(s):
+        return sum(Fraction(t) for t in re.findall(r"[+-]?\d+(?:/\d+)?", s))
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "tv_prox_chambolle_small.txt")
+    cases = []
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        head, xs = line.split("|")
+        f = head.split()
+        name, ny, nx, n_iter = f[0], int(f[1]), int(f[2]), int(f[3])
+        z = np.array([float(value(v)) for v in f[4:]]).reshape(ny, nx)
+        x = np.array([float(value(v)) for v in xs.split()]).reshape(ny, nx)
+        cases.append((f"{name}-n{n_iter}", z, n_iter, x))
+    return cases
+
+
+@pytest.mark.parametrize("name,z,n_iter,expect", _golden_tv_cases(), ids=[c[0] for c in _golden_tv_cases()])
+def test_finite_step_map_matches_hand_derivation(name, z, n_iter, expect):
+    """The n-step map itself (not only its limit) against values worked out by hand in exact
+    fractions: the 1 x 2 recurrence for n = 1..6, its upright twin, two coupled duals of a
+    1 x 3 image for two steps, and one isotropic step on a 2 x 2 image."""
+    x = oracle.tv_prox(z, 1.0 / 64.0, n_iter, 0.125)
+    np.testing.assert_allclose(x, expect, rtol=0, atol=1e-15)
+    # a step more or less gives a different image (the count is pinned, not just the limit)
+    for m in (n_iter - 1, n_iter + 1):
+        if m >= 0:
+            assert np.max(np.abs(oracle.tv_prox(z, 1.0 / 64.0, m, 0.125) - expect)) > 1e-6
+
+
+def _chambolle_dense(z, lam, n_iter, tau):
+    """The same dual steps written on the sparse difference matrix G (div = -G^T), vectorised
+    over pixels: an independent formulation for brute-force comparison on small images."""
+    ny, nx = z.shape
+    G = grad_matrix(ny, nx)
+    n = z.size
+    zf = z.ravel()
+    p = np.zeros(2 * n)
+    for _ in range(n_iter):
+        q = G @ (-(G.T @ p) - zf / lam)
+        mag = np.sqrt(q[:n] ** 2 + q[n:] ** 2)
+        p = (p + tau * q) / np.concatenate([1 + tau * mag, 1 + tau * mag])
+    return (zf + lam * (G.T @ p)).reshape(ny, nx)
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (8, 3), (1, 6), (6, 1)])
+@pytest.mark.parametrize("n_iter", [1, 2, 5, 8])
+def test_finite_step_map_matches_matrix_form(shape, n_iter):
+    rng = np.random.default_rng(10 + n_iter)
+    z = rng.random(shape)
+    x = oracle.tv_prox(z, 0.01, n_iter, 0.125)
+    np.testing.assert_allclose(x, _chambolle_dense(z, 0.01, n_iter, 0.125), rtol=0, atol=1e-12)
