@@ -29,7 +29,9 @@
  *   All array arguments are device pointers (hipMalloc'd or torch tensors) with
  *   at least 16-byte alignment; the caller owns them. Calls are asynchronous on
  *   the given stream and never synchronise, allocate or free, except the
- *   plan/graph create and destroy calls and fb_power_lipschitz (documented).
+ *   set-up calls that say so (plan, batch and graph creation and
+ *   destruction, configuration and sketch changes of a batch or plan,
+ *   fb_batch_prepare, the autotuners) and fb_power_lipschitz.
  *   A plan owns a device workspace: calls that use one plan must not overlap
  *   in time (issue them on one stream, or use one plan per stream).
  *   Outputs never alias inputs unless a call says otherwise.
@@ -99,6 +101,11 @@ typedef struct fb_stage_info {
 fb_status fb_plan_stage_info(const fb_plan* plan, int stage, fb_stage_info* out);
 /* The same sample count per view: out is a host array of n_views entries. */
 fb_status fb_plan_view_samples(const fb_plan* plan, int stage, int64_t* out);
+/* Device workspace that calls at this stage use, in bytes: the stage's two
+ * line images, the residual [n_views][n_bins] and z [ny][nx]. The plan owns
+ * it (allocated once by fb_plan_create), so fanbeam_fp, fanbeam_bp and
+ * pnp_step take no workspace argument; the figure is for memory accounting. */
+fb_status fb_workspace_bytes(const fb_plan* plan, int stage, size_t* out);
 
 /*
  * Sketch operator of the plan's stages with f > 1 (Sec. 2.1, Eqs. (4), (6)):
@@ -182,6 +189,7 @@ size_t fb_tv_workspace_bytes(int nx, int ny, int n_iter);
 fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_iter, float tau, void* ws,
                   size_t ws_bytes, hipStream_t stream);
 
+
 /*
  * One PnP-MS2G iteration t (Sec. 2.1, Algorithm 1, Option 1 or 2):
  *   v   = S_k(y_{t-1})                        (pooling of the stage)
@@ -212,7 +220,7 @@ fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_
  * Variance-reduced gradients (SVRG over view subsets; the estimators named
  * after Eq. (7)), by vr_mode:
  *   0  the minibatch gradient above (snap_proj, snap_grad unused);
- *   1  snapshot: every view (views NULL, n_sel = n_views, sigma 1); the step
+ *   1  snapshot: every view (views NULL, n_sub <= 1, n_sel = n_views, sigma 1); the step
  *      is the full-gradient step, and it also stores the snapshot's projection
  *      A_s v into snap_proj (device [n_views][n_bins]) and its coarse gradient
  *      A_s^T (A_s v - b) into snap_grad (device [nys][nxs] of the stage);
@@ -277,9 +285,16 @@ fb_status fb_graph_destroy(fb_graph* graph);
  *     step sizes. n_sub <= 1 selects all views; n_sub > 1 selects views
  *     k = subset + n_sub i of every slice (the gradient is then usually scaled
  *     by sigma = n_sub). history (optional) is an image arena receiving x_t.
- *     next_stage / prepared / events as in fb_pnp_args. A step's work lists
- *     are built on its first use, which cannot happen under stream capture:
- *     capture with fb_batch_graph_create, which builds them first.
+ *     next_stage / prepared / events as in fb_pnp_args. A step never
+ *     allocates or synchronises: it reads per-launch work lists (the
+ *     (slice, block) order of its work-groups) that set-up calls build.
+ *     fb_batch_create builds those of all-view steps (n_sub <= 1);
+ *     fb_batch_prepare(batch, n_sub) builds those of steps with n_sub
+ *     subsets (allocates and synchronises the device). Later
+ *     configuration changes (fb_batch_set_config, fb_batch_autotune) rebuild
+ *     the lists of every subset count prepared so far, and
+ *     fb_batch_graph_create builds whatever its steps need before capture.
+ *     A step whose lists are missing returns FB_EINVAL and launches nothing.
  *   fb_batch_set_config / fb_batch_get_config: launch configuration per
  *     stage, as for plans (get: the one used with n_sub subsets).
  */
@@ -307,6 +322,7 @@ fb_status fb_batch_layout(const fb_batch* batch, int64_t* image_offsets, int64_t
 fb_status fb_batch_slice_plan(fb_batch* batch, int slice, fb_plan** out);
 fb_status fb_batch_set_config(fb_batch* batch, int stage, const fb_launch_config* cfg);
 fb_status fb_batch_get_config(const fb_batch* batch, int stage, int n_sub, fb_launch_config* out);
+fb_status fb_batch_prepare(fb_batch* batch, int n_sub);
 fb_status pnp_step_batched(fb_batch* batch, const fb_batch_args* args, hipStream_t stream);
 fb_status fb_batch_graph_create(fb_batch* batch, const fb_batch_args* steps, int n_steps, fb_graph** out);
 
@@ -348,7 +364,8 @@ fb_status tv_prox_vjp(const float* z, const float* xbar, float* zbar, int nx, in
  * sketched gradient G (the matched projector pair serves as its own adjoint).
  * combine != 0 writes ybar_prev + xbar_prev into ybar_prev (the adjoint of
  * x_0 when x_0 = y_0). Outputs must not alias inputs or each other. Uses the
- * plan workspace and ws (at least fb_pnp_vjp_workspace_bytes(plan, tv_iters)).
+ * plan workspace and ws (at least fb_pnp_vjp_workspace_bytes(plan, tv_iters)
+ * bytes, 256-byte aligned, as torch and hipMalloc allocations are).
  */
 size_t fb_pnp_vjp_workspace_bytes(const fb_plan* plan, int tv_iters);
 fb_status pnp_step_vjp(const fb_plan* plan, const fb_pnp_args* args, const float* xbar, const float* ybar,

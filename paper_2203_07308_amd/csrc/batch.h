@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <map>
+#include <set>
 #include <tuple>
 #include <vector>
 
@@ -51,11 +52,23 @@ struct fb_batch {
     std::vector<int64_t> img_off, sino_off;  // n_slices + 1 entries
     std::vector<fb_launch_config> cfg;       // per stage; zero fields: defaults
     std::map<std::tuple<int, int, int, int>, fbpnp::ItemTable> tables;
+    std::set<int> prepared;  // subset counts whose work lists follow every configuration change
+    bool building = false;   // set-up calls only: missing work lists may be built (allocates, synchronises)
 };
 
 namespace fbpnp {
 
 fb_launch_config batch_config(const fb_batch* B, int stage, int n_sub);
+// Builds every work list that steps with n_sub subsets use under the current
+// launch configurations (a set-up call: allocates and synchronises).
+fb_status ensure_tables(fb_batch* B, int n_sub);
+// Scoped permission for a set-up call to build missing work lists.
+struct BuildScope {
+    fb_batch* B;
+    bool was;
+    explicit BuildScope(fb_batch* b) : B(b), was(b->building) { B->building = true; }
+    ~BuildScope() { B->building = was; }
+};
 fb_status launch_prepare_batch(fb_batch* B, int stage, const float* y, hipStream_t s);
 fb_status launch_fp_batch(fb_batch* B, int stage, int n_sub, int subset, const float* b, int seg, hipStream_t s);
 fb_status launch_bp_batch(fb_batch* B, int stage, int n_sub, int subset, const float* eta, float sigma,

@@ -161,19 +161,20 @@ fb_launch_config batch_config(const fb_batch* B, int stage, int n_sub) {
 // Work-item table of one launch kind: slices in longest-processing-time
 // order, each contributing its blocks in order. kind: 0 pooling, 1 forward
 // projection (param = fp_seg), 2 backprojection (param = bp_px), 3 TV (param =
-// tile side). Built on first use and kept.
-static fb_status work_items(fb_batch* B, int kind, int stage, int param, int n_sub, hipStream_t stream,
-                            const ItemTable** out) {
+// tile side). Tables are built by set-up calls (batch creation, configuration
+// changes, fb_batch_prepare, the autotuner, graph creation); a step only looks
+// them up, so it never allocates or synchronises.
+static fb_status work_items(fb_batch* B, int kind, int stage, int param, int n_sub, const ItemTable** out) {
     const auto key = std::make_tuple(kind, stage, param, n_sub);
     auto found = B->tables.find(key);
     if (found != B->tables.end()) {
         *out = &found->second;
         return FB_OK;
     }
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (stream && hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
-        return fail(FB_EINVAL, "batch: a work list is built on first use, which cannot happen under stream capture "
-                               "(run the step once first, or use fb_batch_graph_create)");
+    if (!B->building)
+        return fail(FB_EINVAL, "batch: no work list for " + std::to_string(n_sub) +
+                                   " subset(s) under the current launch configuration; call fb_batch_prepare "
+                                   "first (set-up calls build them)");
     const int n = (int)B->h_desc.size();
     std::vector<long> blocks(n), cost(n);
     for (int i = 0; i < n; ++i) {
@@ -226,7 +227,7 @@ static fb_status work_items(fb_batch* B, int kind, int stage, int param, int n_s
 
 fb_status launch_fp_batch(fb_batch* B, int stage, int n_sub, int subset, const float* b, int seg, hipStream_t s) {
     const ItemTable* t;
-    fb_status st = work_items(B, 1, stage, seg, n_sub, s, &t);
+    fb_status st = work_items(B, 1, stage, seg, n_sub, &t);
     if (st != FB_OK) return st;
     if (seg == 8) FB_BLAUNCH(k_fp_batch<8>, dim3(t->n), dim3(256), s, B->d_desc, t->d, stage, subset, n_sub, b);
     else if (seg == 4) FB_BLAUNCH(k_fp_batch<4>, dim3(t->n), dim3(256), s, B->d_desc, t->d, stage, subset, n_sub, b);
@@ -249,7 +250,7 @@ fb_status launch_bp_batch(fb_batch* B, int stage, int n_sub, int subset, const f
     const bool all_bins = batch_all_bins(B, stage, px);
     if (all_bins) px = 1;
     const ItemTable* t;
-    fb_status st = work_items(B, 2, stage, px, n_sub, s, &t);
+    fb_status st = work_items(B, 2, stage, px, n_sub, &t);
     if (st != FB_OK) return st;
     if (all_bins) {
         FB_BLAUNCH((k_bp_batch<4, 1, true>), dim3(t->n), dim3(256), s, B->d_desc, t->d, stage, subset, n_sub, eta,
@@ -288,7 +289,7 @@ fb_status launch_tv_batch(fb_batch* B, int next_stage, float lam, float tau, int
     if (next_stage >= 0 && tile % B->factors[next_stage] != 0)
         return fail(FB_EINVAL, "pooling factor does not divide the TV tile");
     const ItemTable* t;
-    fb_status st = work_items(B, 3, 0, tile, 1, s, &t);
+    fb_status st = work_items(B, 3, 0, tile, 1, &t);
     if (st != FB_OK) return st;
 #define FB_TVB(TT, HH, NT)                                                                                      \
     FB_BLAUNCH((k_tv_batch<TT, HH, NT>), dim3(t->n), dim3(NT), s, B->d_desc, t->d, next_stage, lam, tau, n_iter, \
@@ -306,7 +307,7 @@ fb_status launch_tv_batch(fb_batch* B, int next_stage, float lam, float tau, int
 
 fb_status launch_prepare_batch(fb_batch* B, int stage, const float* y, hipStream_t s) {
     const ItemTable* t;
-    fb_status st = work_items(B, 0, stage, 0, 1, s, &t);
+    fb_status st = work_items(B, 0, stage, 0, 1, &t);
     if (st != FB_OK) return st;
     k_prepare_batch<<<t->n, 256, 0, s>>>(B->d_desc, t->d, stage, y);
     return check_launch("batched prepare");
@@ -326,17 +327,21 @@ static fb_status check_batch_args(const fb_batch* B, const fb_batch_args* a) {
     return FB_OK;
 }
 
-// Builds every work list the step will use (outside any capture).
-static fb_status warm_tables(fb_batch* B, const fb_batch_args* a) {
-    const int n_sub = std::max(1, a->n_sub);
-    const fb_launch_config c = batch_config(B, a->stage, n_sub);
+fb_status ensure_tables(fb_batch* B, int n_sub) {
+    n_sub = std::max(1, n_sub);
+    BuildScope scope(B);
     const ItemTable* t;
     fb_status st;
-    if ((st = work_items(B, 0, a->stage, 0, 1, nullptr, &t)) != FB_OK) return st;
-    if ((st = work_items(B, 1, a->stage, c.fp_seg, n_sub, nullptr, &t)) != FB_OK) return st;
-    const int bp_px = batch_all_bins(B, a->stage, c.bp_px) ? 1 : c.bp_px;  // as launch_bp_batch chooses
-    if ((st = work_items(B, 2, a->stage, bp_px, n_sub, nullptr, &t)) != FB_OK) return st;
-    return work_items(B, 3, 0, c.tv_tile, 1, nullptr, &t);
+    for (int k = 0; k < B->n_stages; ++k) {
+        const fb_launch_config c = batch_config(B, k, n_sub);
+        if ((st = work_items(B, 0, k, 0, 1, &t)) != FB_OK) return st;
+        if ((st = work_items(B, 1, k, c.fp_seg, n_sub, &t)) != FB_OK) return st;
+        const int bp_px = batch_all_bins(B, k, c.bp_px) ? 1 : c.bp_px;  // as launch_bp_batch chooses
+        if ((st = work_items(B, 2, k, bp_px, n_sub, &t)) != FB_OK) return st;
+        if ((st = work_items(B, 3, 0, c.tv_tile, 1, &t)) != FB_OK) return st;
+    }
+    B->prepared.insert(n_sub);
+    return FB_OK;
 }
 
 }  // namespace fbpnp
@@ -407,6 +412,11 @@ fb_status fb_batch_create(const fb_geom* geoms, int n_slices, int n_stages, cons
         fb_batch_destroy(B);
         return hip_fail(e, "fb_batch_create: descriptor upload");
     }
+    fb_status st = ensure_tables(B, 1);  // steps over all views need no further set-up
+    if (st != FB_OK) {
+        fb_batch_destroy(B);
+        return st;
+    }
     *out = B;
     return FB_OK;
 }
@@ -439,8 +449,19 @@ fb_status fb_batch_set_config(fb_batch* B, int stage, const fb_launch_config* cf
     const fb_launch_config c = cfg ? *cfg : fb_launch_config{0, 0, 0, 0};
     fb_status st = check_config(c);
     if (st != FB_OK) return st;
+    const fb_launch_config old = B->cfg[stage];
     B->cfg[stage] = c;
+    for (int n_sub : std::set<int>(B->prepared))
+        if ((st = ensure_tables(B, n_sub)) != FB_OK) {
+            B->cfg[stage] = old;
+            return st;
+        }
     return FB_OK;
+}
+
+fb_status fb_batch_prepare(fb_batch* B, int n_sub) {
+    if (!B || n_sub < 0) return fail(FB_EINVAL, "fb_batch_prepare: bad arguments");
+    return ensure_tables(B, n_sub);
 }
 
 fb_status fb_batch_get_config(const fb_batch* B, int stage, int n_sub, fb_launch_config* out) {
@@ -490,7 +511,7 @@ fb_status fb_batch_graph_create(fb_batch* B, const fb_batch_args* steps, int n_s
         chain[i].prepared = 0;
         chain[i].next_stage = -1;
         chain[i].events = nullptr;  // kernel timing is for direct calls only
-        if ((st = warm_tables(B, &chain[i])) != FB_OK) return st;
+        if ((st = ensure_tables(B, chain[i].n_sub)) != FB_OK) return st;
     }
     // step i pools its y_t for step i + 1 when that step reads it
     for (int i = 0; i + 1 < n_steps; ++i) {

@@ -506,6 +506,16 @@ fb_status fb_plan_get_config(const fb_plan* p, int stage, int n_sel, fb_launch_c
     return FB_OK;
 }
 
+fb_status fb_workspace_bytes(const fb_plan* p, int stage, size_t* out) {
+    fb_status st = check_stage(p, stage);
+    if (st != FB_OK) return st;
+    if (!out) return fail(FB_EINVAL, "out is NULL");
+    const StageLines L = stage_lines(p, stage);
+    *out = (size_t)L.bytes + (size_t)p->g.n_views * p->g.n_bins * sizeof(float) +
+           (size_t)p->g.nx * p->g.ny * sizeof(float);
+    return FB_OK;
+}
+
 fb_status fb_plan_view_samples(const fb_plan* p, int stage, int64_t* out) {
     fb_status st = check_stage(p, stage);
     if (st != FB_OK) return st;
@@ -555,11 +565,14 @@ size_t fb_tv_workspace_bytes(int nx, int ny, int n_iter) {
     return 4 * (size_t)nx * ny * sizeof(float);
 }
 
-fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_iter, float tau, void* ws,
-                  size_t ws_bytes, hipStream_t stream) {
-    if (!z || !x || nx < 1 || ny < 1 || n_iter < 0) return fail(FB_EINVAL, "tv_prox: bad arguments");
-    if (!(lambda >= 0.f) || !(tau > 0.f)) return fail(FB_EINVAL, "tv_prox: need lambda >= 0 and tau > 0");
-    if (z == x) return fail(FB_EINVAL, "tv_prox: z and x must not alias");
+}  // extern "C"
+
+// The denoiser after its arguments are checked. ws: the two dual fields
+// [2][ny][nx] of the multi-launch ping-pong, used only when n_iter > 8 (every
+// cell is written by one launch before the next one reads it, so ws needs no
+// clearing).
+static fb_status tv_prox_run(const float* z, float* x, int nx, int ny, float lambda, int n_iter, float tau,
+                             float* ws, hipStream_t stream) {
     if (lambda == 0.f || n_iter == 0) {
         hipError_t e = hipMemcpyAsync(x, z, (size_t)nx * ny * sizeof(float), hipMemcpyDeviceToDevice, stream);
         return e == hipSuccess ? FB_OK : hip_fail(e, "tv_prox copy");
@@ -567,9 +580,7 @@ fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_
     if (n_iter <= kTvMaxFused)
         return launch_tv_single(z, nx, ny, lambda, tau, n_iter, nullptr, nullptr, 0, 0.f, 0.f, nullptr, x, nullptr,
                                 nullptr, stream);
-    const size_t need = fb_tv_workspace_bytes(nx, ny, n_iter);
-    if (!ws || ws_bytes < need) return fail(FB_EINVAL, "tv_prox: workspace too small");
-    float* pa = (float*)ws;
+    float* pa = ws;
     float* pb = pa + 2 * (size_t)nx * ny;
     const float* pin = nullptr;
     int left = n_iter;
@@ -586,6 +597,27 @@ fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_
     return launch_tv_single(z, nx, ny, lambda, tau, 0, pin, nullptr, 0, 0.f, 0.f, nullptr, x, nullptr, nullptr,
                             stream);
 }
+
+static fb_status tv_prox_check(const char* who, const float* z, const float* x, int nx, int ny, float lambda,
+                               int n_iter, float tau) {
+    const std::string w(who);
+    if (!z || !x || nx < 1 || ny < 1 || n_iter < 0) return fail(FB_EINVAL, w + ": bad arguments");
+    if (!(lambda >= 0.f) || !(tau > 0.f)) return fail(FB_EINVAL, w + ": need lambda >= 0 and tau > 0");
+    if (z == x) return fail(FB_EINVAL, w + ": z and x must not alias");
+    return FB_OK;
+}
+
+extern "C" {
+
+fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_iter, float tau, void* ws,
+                  size_t ws_bytes, hipStream_t stream) {
+    fb_status st = tv_prox_check("tv_prox", z, x, nx, ny, lambda, n_iter, tau);
+    if (st != FB_OK) return st;
+    if (n_iter > kTvMaxFused && lambda != 0.f && (!ws || ws_bytes < fb_tv_workspace_bytes(nx, ny, n_iter)))
+        return fail(FB_EINVAL, "tv_prox: workspace too small");
+    return tv_prox_run(z, x, nx, ny, lambda, n_iter, tau, (float*)ws, stream);
+}
+
 
 // The TV epilogue's hand-over of y_t to the next step's stage: its pooling
 // into that stage's line images (not for bicubic stages, which sketch anew).
@@ -664,8 +696,9 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
     if (a->vr_mode < 0 || a->vr_mode > 2) return fail(FB_EINVAL, "pnp_step: vr_mode must be 0, 1 or 2");
     if (a->vr_mode && (!a->snap_proj || !a->snap_grad))
         return fail(FB_EINVAL, "pnp_step: variance-reduced modes need snap_proj and snap_grad");
-    if (a->vr_mode == 1 && a->n_sel != p->g.n_views)
-        return fail(FB_ESUBSET, "pnp_step: a snapshot step uses every view");
+    // a snapshot fills every row of snap_proj: all views, in order, each once
+    if (a->vr_mode == 1 && (a->views || a->n_sub > 1 || a->n_sel != p->g.n_views))
+        return fail(FB_EINVAL, "pnp_step: a snapshot step takes every view (views NULL, no subset)");
     const Stage& S = p->stages[a->stage];
     if (bicubic_stage(p, a->stage)) return pnp_step_bicubic(p, a, stream);
     if (!a->prepared && (st = launch_prepare(p, a->stage, a->y_prev, p->g.nx, S.f, stream)) != FB_OK) return st;

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <fstream>
 #include <functional>
+#include <set>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -33,15 +34,24 @@ constexpr float kMargin = 0.03f;  // a candidate replaces the default only if >=
 
 struct DevBuf {
     void* p = nullptr;
+    size_t bytes = 0;
     ~DevBuf() {
         if (p) (void)hipFree(p);
     }
-    fb_status alloc(size_t bytes) {
-        return hipMalloc(&p, std::max<size_t>(bytes, 4)) == hipSuccess ? FB_OK
-                                                                        : fail(FB_ENOMEM, "autotune: allocation");
+    fb_status alloc(size_t n) {
+        if (hipMalloc(&p, std::max<size_t>(n, 4)) != hipSuccess) return fail(FB_ENOMEM, "autotune: allocation");
+        bytes = n;
+        return FB_OK;
     }
     float* f() const { return (float*)p; }
 };
+
+// Host-side check, before the launches that use it, that a scratch buffer
+// holds what they read or write (floats).
+fb_status need(const DevBuf& d, size_t floats, const char* what) {
+    if (d.bytes >= floats * sizeof(float)) return FB_OK;
+    return fail(FB_EINVAL, std::string("autotune: scratch buffer too small for ") + what);
+}
 
 // Smooth deterministic test data in [0, 1): a sum of two products of sines.
 std::vector<float> pattern(size_t n, int period, float phase) {
@@ -255,6 +265,15 @@ static fb_status autotune_plan(fb_plan* p, int n_sel, const char* cache_path, hi
             continue;
         }
         const size_t ncoarse = (size_t)S.nxs * S.nys;
+        // what the candidate launches below read and write
+        if ((st = need(img, npix, "the image pooled into the line images")) != FB_OK ||
+            (st = need(b, (size_t)V * nb, "the data b")) != FB_OK ||
+            (st = need(proj, nproj, "the residual projection")) != FB_OK ||
+            (st = need(sino, nproj, "the back-projected sinogram")) != FB_OK ||
+            (st = need(yprev, npix, "y_prev")) != FB_OK || (st = need(out, ncoarse, "the coarse gradient")) != FB_OK ||
+            (st = need(out, npix, "the denoised image")) != FB_OK || (st = need(xprev, npix, "x_prev")) != FB_OK ||
+            (st = need(views, (size_t)n_sel, "the view list")) != FB_OK)
+            return st;
         p->cfg[k] = fb_launch_config{0, 0, 0, 0};
         const fb_launch_config def = plan_config(p, k, n_sel);
         if ((st = launch_prepare(p, k, img.f(), nx, S.f, s)) != FB_OK) return st;
@@ -314,6 +333,7 @@ static fb_status autotune_plan(fb_plan* p, int n_sel, const char* cache_path, hi
 
 static fb_status autotune_batch(fb_batch* B, int n_sub, const char* cache_path, hipStream_t s) {
     n_sub = std::max(1, n_sub);
+    BuildScope scope(B);  // candidates launch with work lists of their own
     const int n = (int)B->h_desc.size();
     const int64_t img_n = B->img_off.back(), sino_n = B->sino_off.back();
     DevBuf img, b, eta, xo, yo, xp;
@@ -352,6 +372,14 @@ static fb_status autotune_batch(fb_batch* B, int n_sub, const char* cache_path, 
             B->cfg[k] = best;
             continue;
         }
+        // what the candidate launches below read and write (the residuals and z
+        // images they write belong to the slice plans)
+        if ((st = need(img, (size_t)img_n, "the image arena")) != FB_OK ||
+            (st = need(b, (size_t)sino_n, "the sinogram arena")) != FB_OK ||
+            (st = need(eta, (size_t)n, "the step sizes")) != FB_OK ||
+            (st = need(xp, (size_t)img_n, "x_prev")) != FB_OK || (st = need(xo, (size_t)img_n, "x_out")) != FB_OK ||
+            (st = need(yo, (size_t)img_n, "y_out")) != FB_OK)
+            return st;
         B->cfg[k] = fb_launch_config{0, 0, 0, 0};
         const fb_launch_config def = batch_config(B, k, n_sub);
         if ((st = launch_prepare_batch(B, k, img.f(), s)) != FB_OK) return st;
@@ -411,6 +439,12 @@ fb_status fb_batch_autotune(fb_batch* B, int n_sub, const char* cache_path, hipS
     if (!B) return fail(FB_EINVAL, "fb_batch_autotune: batch is NULL");
     const std::vector<fb_launch_config> saved = B->cfg;
     fb_status st = autotune_batch(B, n_sub, cache_path, s);
+    // steps with the tuned subset count, and with every count prepared before,
+    // find their work lists under the chosen configuration
+    std::set<int> counts = B->prepared;
+    counts.insert(std::max(1, n_sub));
+    for (int n : counts)
+        if (st == FB_OK) st = ensure_tables(B, n);
     if (st != FB_OK) B->cfg = saved;
     return st;
 }

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 
 #include "fbpnp_impl.h"
 
@@ -228,11 +229,18 @@ fb_status tv_prox_vjp(const float* z, const float* xbar, float* zbar, int nx, in
     return launch_tv_vjp(z, xbar, zbar, nx, ny, lambda, n_iter, tau, alpha, (float*)ws, stream);
 }
 
+// Float offset of the double-precision reduction partials in a pnp_step_vjp
+// workspace: after z, xtot, zbar, the coarse gradient and the TV reverse sweep,
+// rounded up to 256 bytes so the doubles are aligned for any image size.
+static size_t vjp_part_offset_floats(int nx, int ny, int tv_iters) {
+    const size_t n = (size_t)nx * ny;
+    return (4 * n + tv_ws_floats(nx, ny, tv_iters) + 63) / 64 * 64;
+}
+
 size_t fb_pnp_vjp_workspace_bytes(const fb_plan* p, int tv_iters) {
     if (!p || tv_iters < 0) return 0;
-    const size_t n = (size_t)p->g.nx * p->g.ny;
-    // z, xtot, zbar, coarse gradient, TV reverse sweep, reduction partials (+1 result)
-    return (4 * n + tv_ws_floats(p->g.nx, p->g.ny, tv_iters)) * sizeof(float) + (kRedBlocks + 2) * sizeof(double);
+    // the float buffers, then the reduction partials (+1 result)
+    return vjp_part_offset_floats(p->g.nx, p->g.ny, tv_iters) * sizeof(float) + (kRedBlocks + 2) * sizeof(double);
 }
 
 fb_status pnp_step_vjp(const fb_plan* p, const fb_pnp_args* a, const float* xbar, const float* ybar, float* xbar_prev,
@@ -248,6 +256,7 @@ fb_status pnp_step_vjp(const fb_plan* p, const fb_pnp_args* a, const float* xbar
     if (!(a->lambda >= 0.f) || !(a->tau > 0.f)) return fail(FB_EINVAL, "pnp_step_vjp: need lambda >= 0 and tau > 0");
     if (!ws || ws_bytes < fb_pnp_vjp_workspace_bytes(p, a->tv_iters))
         return fail(FB_EINVAL, "pnp_step_vjp: workspace too small");
+    if ((uintptr_t)ws % 256 != 0) return fail(FB_EINVAL, "pnp_step_vjp: workspace must be 256-byte aligned");
     const float* outs[] = {xbar_prev, ybar_prev};
     const float* ins[] = {xbar, ybar, a->y_prev, a->x_prev, a->b};
     for (const float* o : outs)
@@ -262,7 +271,7 @@ fb_status pnp_step_vjp(const fb_plan* p, const fb_pnp_args* a, const float* xbar
     float* zbar = xtot + n;
     float* gs = zbar + n;
     float* tvws = gs + n;
-    double* part = (double*)((char*)ws + (4 * n + tv_ws_floats(nx, ny, a->tv_iters)) * sizeof(float));
+    double* part = (double*)((float*)ws + vjp_part_offset_floats(nx, ny, a->tv_iters));
     const dim3 grid(cdiv(nx, 256), ny);
     // forward recomputation: gs = sigma A_s^T M (M A_s S y - M b), z = y - eta U gs
     if ((st = launch_prepare(p, a->stage, a->y_prev, nx, f, stream)) != FB_OK) return st;

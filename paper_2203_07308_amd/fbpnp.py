@@ -25,8 +25,9 @@ EXPORTS = [
     "sketch_down", "sketch_up", "fb_tv_workspace_bytes", "tv_prox", "pnp_step", "fb_graph_create",
     "fb_graph_launch", "fb_graph_destroy", "fb_tv_vjp_workspace_bytes", "tv_prox_vjp",
     "fb_pnp_vjp_workspace_bytes", "pnp_step_vjp", "fb_power_lipschitz", "fb_plan_view_samples",
-    "fb_plan_set_config", "fb_plan_get_config", "fb_batch_create", "fb_batch_destroy", "fb_batch_layout",
-    "fb_batch_slice_plan", "fb_batch_set_config", "fb_batch_get_config", "pnp_step_batched",
+    "fb_workspace_bytes", "fb_plan_set_config", "fb_plan_get_config", "fb_batch_create", "fb_batch_destroy",
+    "fb_batch_layout", "fb_batch_slice_plan", "fb_batch_set_config", "fb_batch_get_config", "fb_batch_prepare",
+    "pnp_step_batched",
     "fb_batch_graph_create", "fb_autotune", "fb_batch_autotune", "fb_plan_set_sketch", "fb_plan_sketch_down",
     "fb_plan_sketch_up",
 ]
@@ -128,6 +129,8 @@ def load() -> ctypes.CDLL:
     lib.fb_batch_slice_plan.argtypes = [vp, c_int, P(vp)]
     lib.fb_batch_set_config.argtypes = [vp, c_int, P(LaunchConfig)]
     lib.fb_batch_get_config.argtypes = [vp, c_int, c_int, P(LaunchConfig)]
+    lib.fb_batch_prepare.argtypes = [vp, c_int]
+    lib.fb_workspace_bytes.argtypes = [vp, c_int, P(ctypes.c_size_t)]
     lib.pnp_step_batched.argtypes = [vp, P(BatchArgs), vp]
     lib.fb_batch_graph_create.argtypes = [vp, P(BatchArgs), c_int, P(vp)]
     lib.fb_autotune.argtypes = [vp, c_int, ctypes.c_char_p, vp]
@@ -259,6 +262,12 @@ class Plan:
         out = StageInfo()
         _check(load().fb_plan_stage_info(self._h, stage, ctypes.byref(out)))
         return out
+
+    def workspace_bytes(self, stage: int) -> int:
+        """Bytes of the plan's own device workspace that calls at this stage use."""
+        out = ctypes.c_size_t()
+        _check(load().fb_workspace_bytes(self._h, stage, ctypes.byref(out)))
+        return out.value
 
     def view_samples(self, stage: int):
         """In-grid Joseph samples of each view at this stage (host list of n_views ints)."""
@@ -458,6 +467,11 @@ class Batch:
     def autotune(self, n_sub: int = 1, cache_path: str | None = None, stream=None) -> None:
         cp = None if cache_path is None else os.fsencode(cache_path)
         _check(load().fb_batch_autotune(self._h, n_sub, cp, _stream(stream)))
+
+    def prepare(self, n_sub: int) -> None:
+        """Builds the work lists of steps with n_sub subsets (a set-up call; steps over all
+        views are prepared at creation)."""
+        _check(load().fb_batch_prepare(self._h, int(n_sub)))
 
     def close(self):
         if getattr(self, "_h", None):

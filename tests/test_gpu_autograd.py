@@ -170,6 +170,33 @@ def test_unrolled_gradients_on_random_geometries(seed):
     assert rel(host(eta_t.grad), r_eta) <= 1e-3, (host(eta_t.grad), r_eta)
 
 
+def test_unrolled_gradients_odd_sized_image():
+    """A 65 x 63 image (an odd pixel count) with 5 TV steps: the reverse pass's double-precision
+    partial sums follow an odd number of floats in its workspace, which must stay aligned."""
+    gd = synth.fan_geometry(65, 40, 100)
+    gd["ny"] = 63
+    og = oracle.Geometry(**gd)
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [1])
+    rng = np.random.default_rng(5)
+    xt = rng.random((63, 65))
+    b = oracle.fp(og, xt).astype(np.float32)
+    T = 3
+    a = synth.momentum_table(T)
+    sched_o = [(1, None, 1.0)] * T
+    specs = [StepSpec(0, None, 1.0, float(a[t])) for t in range(T)]
+    eta = np.full(T, 0.5 / oracle.power_lipschitz(og, 1, 30))
+    x0 = 0.3 * xt
+    say("unrolled odd size 65 x 63")
+    x0_t = dev(x0).requires_grad_(True)
+    eta_t = torch.tensor(eta, dtype=torch.float32, device="cuda", requires_grad=True)
+    xT = unrolled_pnp(plan, dev(b).reshape(-1), specs, x0_t, eta_t)
+    (0.5 * ((xT - dev(xt)) ** 2).sum()).backward()
+    r_x0, r_eta = oracle.pnp_vjp(og, b.astype(np.float64), sched_o, eta, a,
+                                 oracle.pnp_run(og, b.astype(np.float64), sched_o, eta, a, x0=x0) - xt, x0=x0)
+    assert rel(host(x0_t.grad), r_x0) <= 1e-3, rel(host(x0_t.grad), r_x0)
+    assert rel(host(eta_t.grad), r_eta) <= 1e-3, (host(eta_t.grad), r_eta)
+
+
 @pytest.mark.slow
 def test_unrolled_gradients_differentiation_workload():
     """The differentiation workload's shape: 10 unrolled two-stage iterations (5 at f = 2,

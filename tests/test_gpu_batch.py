@@ -108,6 +108,8 @@ def run_batched(batch, b_arena, sched, eta, graph=False, alpha=1.0):
         np.testing.assert_array_equal(host(out1), host(x))  # replays are identical
         g.close()
     else:
+        for n_sub in sorted({s[1] for s in sched}):
+            batch.prepare(n_sub)  # set-up: the work lists of steps with these subset counts
         fbpnp.chain_steps(steps)
         for st in steps:
             fbpnp.pnp_step_batched(batch, st)
@@ -403,5 +405,16 @@ def test_batch_rejects_bad_arguments():
         batch.set_config(0, dict(fp_seg=0, bp_px=4, bp_vg=8, tv_tile=0))
     with pytest.raises(fbpnp.FbError):
         fbpnp.Batch([fbpnp.Geometry(**synth.fan_geometry(63, 30))], [2])  # 2 does not divide 63
+    # a step never builds work lists itself: steps with subsets need a set-up call first
+    y = torch.zeros_like(x)
+    with pytest.raises(fbpnp.FbError, match="fb_batch_prepare"):
+        fbpnp.pnp_step_batched(batch, fbpnp.batch_args(batch, 0, b, y, x, x, y, eta, 0.0, n_sub=3, subset=1,
+                                                       sigma=3.0))
+    batch.prepare(3)
+    fbpnp.pnp_step_batched(batch, fbpnp.batch_args(batch, 0, b, y, x, x, y, eta, 0.0, n_sub=3, subset=1, sigma=3.0))
+    # a configuration change keeps the prepared subset counts runnable
+    batch.set_config(0, dict(fp_seg=1, bp_px=1, bp_vg=2, tv_tile=16))
+    fbpnp.pnp_step_batched(batch, fbpnp.batch_args(batch, 0, b, y, x, x, y, eta, 0.0, n_sub=3, subset=2, sigma=3.0))
+    torch.cuda.synchronize()
     with pytest.raises(ValueError):
         fbpnp.batch_args(batch, 0, b[:10], x, x, x, x, eta, 0.0)

@@ -1,0 +1,228 @@
+"""GPU parity at the workloads' own sizes and schedules, in the launch shapes the benchmark
+runs (the shipped autotuner cache), against the FP64 oracle:
+
+  * the 512^2 multi-stage sketched PnP-SGD schedule (Algorithm 1, Option 2): 720 views x
+    768 bins, 20 iterations each at f = 4, 2, 1, 1 of 8 interleaved view subsets drawn from
+    the benchmark's seeded stream, per-stage steps 1 / L, FISTA momentum, all 60 iterations
+    as one captured graph;
+  * the 64-slice batched workload (widths 128 to 512, 180 / 360 / 720 views, 1.5 x width
+    bins, two-stage sketch) with its tuned batch configuration: every slice bitwise equal to
+    the same slice run alone, and two slices (384^2 x 720 views, 512^2 x 360 views) against
+    the oracle over 5 iterations per stage;
+  * the paper's three 256^2 scan scenarios (Sec. 3) over their whole 25 + 75 two-stage
+    schedule.
+
+Reconstruction bar: relative L2 <= 1e-4 (the reconstruction tolerance of the path). The
+oracle's step sizes for the two larger problems come from tests/golden/oracle_step_sizes.txt
+(written by the oracle alone; 100 power iterations at 512^2 take minutes of host time).
+"""
+import os
+import shutil
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2203_07308_amd import fbpnp, synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SHIPPED_CACHE = os.path.join(ROOT, "paper_2203_07308_amd", "tuned", "mi355x_launch_configs.txt")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fbpnp.load()
+
+
+def dev(a, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def oracle_lipschitz():
+    """{(workload, factor): L} from the committed oracle step-size file."""
+    out = {}
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_step_sizes.txt")) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].split()
+            if line:
+                out[(line[0], int(line[1]))] = float(line[2])
+    return out
+
+
+def tuned_cache(tmp_path):
+    path = tmp_path / "launch_configs.txt"
+    shutil.copyfile(SHIPPED_CACHE, path)
+    return str(path)
+
+
+def test_ms2g512_whole_schedule_as_benchmarked(tmp_path):
+    w = synth.WORKLOADS["ms2g512"]
+    gd = w.geometry
+    og = oracle.Geometry(**gd)
+    V, n_sub = gd["n_views"], w.n_subsets
+    xt = synth.phantom(w)
+    ax = oracle.fp(og, xt.astype(np.float64))
+    b = synth.add_noise(ax, synth.standard_normal(synth.noise_seed(w), ax.shape), w.noise_kind,
+                        w.noise_level).astype(np.float32)
+    L = oracle_lipschitz()
+    factors = [f for f, _ in w.stages]
+    fs = [f for f, n in w.stages for _ in range(n)]
+    T = len(fs)
+    seq = synth.subset_sequence(3000 * w.seed_base, T, n_sub)  # the benchmark's subset stream
+    eta = np.array([1.0 / L[("ms2g512", f)] for f in fs])
+    a = synth.momentum_table(T, w.momentum)
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), factors)
+    plan.autotune(n_sel=V // n_sub, cache_path=tuned_cache(tmp_path))
+    say("ms2g512 whole schedule", [plan.get_config(k, V // n_sub) for k in range(len(factors))])
+    npix = gd["nx"] * gd["ny"]
+    bd = dev(b).reshape(-1)
+    x = torch.zeros(npix, device="cuda")
+    y = torch.zeros(npix, device="cuda")
+    hist = torch.zeros((T, npix), device="cuda")
+    steps = [fbpnp.pnp_args(plan, factors.index(fs[t]), bd, y, x, x, y, float(eta[t]), float(a[t]), None,
+                            float(n_sub), w.alpha, w.lam, w.tau, w.tv_iters, hist[t],
+                            subset=(int(seq[t]), n_sub)) for t in range(T)]
+    g = fbpnp.Graph(plan, steps)
+    g.launch()
+    got, got_hist = host(x).reshape(gd["ny"], gd["nx"]), host(hist)
+    g.close()
+    sched_o = [(fs[t], synth.subset_views(int(seq[t]), n_sub, V), float(n_sub)) for t in range(T)]
+    ref, ref_hist = oracle.pnp_run(og, b.astype(np.float64), sched_o, eta, a, w.alpha, w.lam, w.tv_iters, w.tau,
+                                   history=True)
+    errs = [rel(got_hist[t].reshape(ref.shape), ref_hist[t]) for t in range(T)]
+    say("ms2g512 worst iterate error", max(errs), "final", rel(got, ref))
+    assert rel(got, ref) <= 1e-4, rel(got, ref)
+    assert max(errs) <= 1e-4, (int(np.argmax(errs)), max(errs))
+    # the reconstruction improves on the data: the schedule does what it is for
+    assert oracle.psnr(ref, xt) > 30.0
+
+
+BATCH_ORACLE_SLICES = (3, 24)  # 384^2 x 720 views and 512^2 x 360 views
+
+
+def test_batch64_real_shapes_tuned(tmp_path):
+    bw = synth.BATCH_WORKLOADS["batch64"]
+    shapes = bw.shapes()
+    factors = [f for f, _ in bw.stages]
+    gds = [synth.fan_geometry(n, V) for n, V in shapes]
+    batch = fbpnp.Batch([fbpnp.Geometry(**g) for g in gds], factors)
+    batch.autotune(1, tuned_cache(tmp_path))
+    cfgs = [batch.get_config(k, 1) for k in range(len(factors))]
+    say("batch64 configs", cfgs)
+    L = oracle_lipschitz()
+    b_arena = torch.zeros(batch.sino_size, device="cuda")
+    eta = np.zeros((len(factors), len(gds)), dtype=np.float32)
+    bs = {}
+    for i, g in enumerate(gds):
+        sw = bw.slice_workload(i)
+        xt = synth.phantom(sw, i)
+        eps = synth.standard_normal(synth.noise_seed(sw, i), (g["n_views"], g["n_bins"]))
+        if i in BATCH_ORACLE_SLICES:
+            ax = oracle.fp(oracle.Geometry(**g), xt.astype(np.float64))
+            for k, f in enumerate(factors):
+                eta[k, i] = 1.0 / L[(f"batch64[{i}]", f)]
+        else:
+            # slices compared only with their own single-slice runs: data and steps from the GPU
+            plan = batch.slice_plan(i)
+            axd = torch.empty(g["n_views"] * g["n_bins"], device="cuda")
+            fbpnp.fanbeam_fp(plan, factors.index(1), dev(xt).reshape(-1), axd)
+            ax = host(axd).reshape(eps.shape)
+            for k in range(len(factors)):
+                eta[k, i] = 1.0 / fbpnp.power_lipschitz(plan, k, 30)
+        bs[i] = synth.add_noise(ax, eps, sw.noise_kind, sw.noise_level).astype(np.float32)
+        batch.sinogram(b_arena, i).copy_(dev(bs[i]))
+    n_it = 5
+    stage_t = [0] * n_it + [1] * n_it
+    T = len(stage_t)
+    a = synth.momentum_table(T, bw.momentum)
+    eta_d = [dev(eta[k]) for k in range(len(factors))]
+    x = torch.zeros(batch.image_size, device="cuda")
+    y = torch.zeros(batch.image_size, device="cuda")
+    steps = [fbpnp.batch_args(batch, stage_t[t], b_arena, y, x, x, y, eta_d[stage_t[t]], float(a[t]),
+                              alpha=bw.alpha, lam=bw.lam, tau=bw.tau, tv_iters=bw.tv_iters) for t in range(T)]
+    say("batch64 graph", len(gds), "slices")
+    g = fbpnp.BatchGraph(batch, steps)
+    g.launch()
+    torch.cuda.synchronize()
+    g.close()
+    # every slice alone, same launch configuration, direct chained calls
+    for i, gd in enumerate(gds):
+        plan = fbpnp.Plan(fbpnp.Geometry(**gd), factors)
+        for k, c in enumerate(cfgs):
+            plan.set_config(k, c)
+        npix = gd["nx"] * gd["ny"]
+        xs = torch.zeros(npix, device="cuda")
+        ys = torch.zeros(npix, device="cuda")
+        bd = dev(bs[i]).reshape(-1)
+        st = [fbpnp.pnp_args(plan, stage_t[t], bd, ys, xs, xs, ys, float(eta[stage_t[t], i]), float(a[t]),
+                             None, 1.0, bw.alpha, bw.lam, bw.tau, bw.tv_iters) for t in range(T)]
+        fbpnp.chain_steps(st)
+        for s in st:
+            fbpnp.pnp_step(plan, s)
+        single = host(xs)
+        batched = host(batch.image(x, i)).reshape(-1)
+        if not np.array_equal(single, batched):
+            raise AssertionError(f"slice {i} {shapes[i]}: batched differs from single-slice, "
+                                 f"max |diff| {np.max(np.abs(single - batched))}")
+        plan.close()
+    for i in BATCH_ORACLE_SLICES:
+        gd = gds[i]
+        sched_o = [(factors[k], None, 1.0) for k in stage_t]
+        et = np.array([eta[k, i] for k in stage_t], dtype=np.float64)
+        ref = oracle.pnp_run(oracle.Geometry(**gd), bs[i].astype(np.float64), sched_o, et, a, bw.alpha, bw.lam,
+                             bw.tv_iters, bw.tau)
+        got = host(batch.image(x, i)).reshape(ref.shape)
+        say("batch64 slice vs oracle", i, shapes[i], rel(got, ref))
+        assert rel(got, ref) <= 1e-4, (i, rel(got, ref))
+    batch.close()
+
+
+@pytest.mark.parametrize("name", sorted(synth.SCENARIOS))
+def test_scenario_whole_schedule(name):
+    """25 iterations at f = 4, then 75 at f = 2 (m1 = d/16, m2 = d/4), all views, Poisson log data,
+    FISTA momentum, one captured graph, against the oracle's loop."""
+    sc = synth.SCENARIOS[name]
+    g = sc.geometry
+    og = oracle.Geometry(**g)
+    x = sc.phantom()
+    b = sc.data(oracle.fp(og, x.astype(np.float64))).astype(np.float32)
+    plan = fbpnp.Plan(fbpnp.Geometry(**g), [4, 2])
+    L4, L2 = oracle.power_lipschitz(og, 4, 100), oracle.power_lipschitz(og, 2, 100)
+    fs = [4] * 25 + [2] * 75
+    T = len(fs)
+    eta = np.array([1 / L4 if f == 4 else 1 / L2 for f in fs])
+    a = synth.momentum_table(T)
+    say("scenario whole schedule", name)
+    npix = g["nx"] * g["ny"]
+    xb = torch.zeros(npix, device="cuda")
+    yb = torch.zeros(npix, device="cuda")
+    bd = dev(b).reshape(-1)
+    steps = [fbpnp.pnp_args(plan, 0 if fs[t] == 4 else 1, bd, yb, xb, xb, yb, float(eta[t]), float(a[t]), None,
+                            1.0, sc.alpha, sc.lam, sc.tau, sc.tv_iters) for t in range(T)]
+    gr = fbpnp.Graph(plan, steps)
+    gr.launch()
+    got = host(xb).reshape(g["ny"], g["nx"])
+    gr.close()
+    ref = oracle.pnp_run(og, b.astype(np.float64), [(f, None, 1.0) for f in fs], eta, a, sc.alpha, sc.lam,
+                         sc.tv_iters, sc.tau)
+    say("scenario", name, rel(got, ref))
+    assert rel(got, ref) <= 1e-4, (name, rel(got, ref))

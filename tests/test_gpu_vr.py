@@ -176,6 +176,11 @@ def test_svrg_argument_checks():
     with pytest.raises(fbpnp.FbError):  # a snapshot needs every view
         fbpnp.pnp_step(plan, fbpnp.pnp_args(plan, 0, bd, x, x, x, x, 1e-4, 0.0, sub, 3.0, vr_mode=1,
                                             snap_proj=sp, snap_grad=sg))
+    # ... each once: a list of n_views entries with repeats would leave rows of snap_proj stale
+    rep = dev(np.repeat(np.arange(45, dtype=np.int32), 2), np.int32)
+    with pytest.raises(fbpnp.FbError):
+        fbpnp.pnp_step(plan, fbpnp.pnp_args(plan, 0, bd, x, x, x, x, 1e-4, 0.0, rep, 1.0, vr_mode=1,
+                                            snap_proj=sp, snap_grad=sg))
     a = fbpnp.pnp_args(plan, 0, bd, x, x, x, x, 1e-4, 0.0, vr_mode=2, snap_proj=sp, snap_grad=sg)
     a.snap_grad = None
     with pytest.raises(fbpnp.FbError):
