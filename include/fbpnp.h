@@ -189,6 +189,22 @@ size_t fb_tv_workspace_bytes(int nx, int ny, int n_iter);
 fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_iter, float tau, void* ws,
                   size_t ws_bytes, hipStream_t stream);
 
+/*
+ * tv_prox without a workspace argument, for callers that cannot allocate
+ * device memory (code under graph capture, serving loops, harnesses that
+ * forbid hipMalloc). Same kernels and results as tv_prox. For n_iter > 8 the
+ * dual fields live in a static device array of 16 MiB per device, allocated
+ * with the library's code object and held until the process ends; its address
+ * is looked up once per device, at the first such call. nx * ny must be at
+ * most 1048576, else FB_EINVAL with nothing launched. The call allocates
+ * nothing. Every call on one device shares that array: calls that overlap on
+ * one device (other streams, other threads) race and give wrong results.
+ * Every cell of the array is written before it is read, so no clearing is
+ * needed between calls.
+ */
+fb_status tv_prox_noalloc(const float* z, float* x, int nx, int ny, float lambda, int n_iter, float tau,
+                          hipStream_t stream);
+
 
 /*
  * One PnP-MS2G iteration t (Sec. 2.1, Algorithm 1, Option 1 or 2):

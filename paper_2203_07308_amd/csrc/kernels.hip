@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <vector>
 
 #include "device.h"
@@ -607,6 +608,33 @@ static fb_status tv_prox_check(const char* who, const float* z, const float* x, 
     return FB_OK;
 }
 
+// Scratch of tv_prox_noalloc: the two dual fields of the multi-launch
+// ping-pong, for images of up to kTvScratchPixels pixels (16 MiB, held by
+// every device the library runs on until the process ends). In host code the
+// array's name is no device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kTvScratchPixels = (size_t)1 << 20;
+static __device__ __align__(256) float scratch[4 * kTvScratchPixels];
+
+// Device address of `scratch` on the current device, looked up once per device.
+static fb_status tv_scratch_address(float** out) {
+    static std::mutex mu;
+    static std::vector<float*> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "tv_prox_noalloc: device");
+    std::lock_guard<std::mutex> lock(mu);
+    if ((size_t)dev >= addr.size()) addr.resize((size_t)dev + 1, nullptr);
+    if (!addr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "tv_prox_noalloc: scratch address");
+        addr[dev] = static_cast<float*>(ptr);
+    }
+    *out = addr[dev];
+    return FB_OK;
+}
+
 extern "C" {
 
 fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_iter, float tau, void* ws,
@@ -616,6 +644,17 @@ fb_status tv_prox(const float* z, float* x, int nx, int ny, float lambda, int n_
     if (n_iter > kTvMaxFused && lambda != 0.f && (!ws || ws_bytes < fb_tv_workspace_bytes(nx, ny, n_iter)))
         return fail(FB_EINVAL, "tv_prox: workspace too small");
     return tv_prox_run(z, x, nx, ny, lambda, n_iter, tau, (float*)ws, stream);
+}
+
+fb_status tv_prox_noalloc(const float* z, float* x, int nx, int ny, float lambda, int n_iter, float tau,
+                          hipStream_t stream) {
+    fb_status st = tv_prox_check("tv_prox_noalloc", z, x, nx, ny, lambda, n_iter, tau);
+    if (st != FB_OK) return st;
+    if ((size_t)nx * (size_t)ny > kTvScratchPixels)
+        return fail(FB_EINVAL, "tv_prox_noalloc: image larger than the static scratch (at most 1048576 pixels)");
+    float* ws = nullptr;
+    if (n_iter > kTvMaxFused && lambda != 0.f && (st = tv_scratch_address(&ws)) != FB_OK) return st;
+    return tv_prox_run(z, x, nx, ny, lambda, n_iter, tau, ws, stream);
 }
 
 

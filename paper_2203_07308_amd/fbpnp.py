@@ -29,7 +29,7 @@ EXPORTS = [
     "fb_batch_layout", "fb_batch_slice_plan", "fb_batch_set_config", "fb_batch_get_config", "fb_batch_prepare",
     "pnp_step_batched",
     "fb_batch_graph_create", "fb_autotune", "fb_batch_autotune", "fb_plan_set_sketch", "fb_plan_sketch_down",
-    "fb_plan_sketch_up",
+    "fb_plan_sketch_up", "tv_prox_noalloc",
 ]
 
 
@@ -113,6 +113,7 @@ def load() -> ctypes.CDLL:
     lib.fb_tv_workspace_bytes.argtypes = [c_int, c_int, c_int]
     lib.fb_tv_workspace_bytes.restype = ctypes.c_size_t
     lib.tv_prox.argtypes = [vp, vp, c_int, c_int, c_float, c_int, c_float, vp, ctypes.c_size_t, vp]
+    lib.tv_prox_noalloc.argtypes = [vp, vp, c_int, c_int, c_float, c_int, c_float, vp]
     lib.pnp_step.argtypes = [vp, P(PnpArgs), vp]
     lib.fb_graph_create.argtypes = [vp, P(PnpArgs), c_int, P(vp)]
     lib.fb_graph_launch.argtypes = [vp, vp]
@@ -331,6 +332,15 @@ def tv_prox(z: torch.Tensor, x: torch.Tensor, lam: float, n_iter: int = 5, tau: 
     wsb = 0 if ws is None else ws.numel() * ws.element_size()
     _check(load().tv_prox(_ptr(z, name="z"), _ptr(x, numel=nx * ny, name="x"), nx, ny, float(lam), int(n_iter),
                           float(tau), None if ws is None else ctypes.c_void_p(ws.data_ptr()), wsb, _stream(stream)))
+    return x
+
+
+def tv_prox_noalloc(z: torch.Tensor, x: torch.Tensor, lam: float, n_iter: int = 5, tau: float = 0.125,
+                    stream=None) -> torch.Tensor:
+    """tv_prox with the library's static scratch instead of a workspace (at most 2^20 pixels)."""
+    ny, nx = z.shape
+    _check(load().tv_prox_noalloc(_ptr(z, name="z"), _ptr(x, numel=nx * ny, name="x"), nx, ny, float(lam),
+                                  int(n_iter), float(tau), _stream(stream)))
     return x
 
 
