@@ -29,15 +29,17 @@ if ROOT not in sys.path:
 
 # MI355X published figures used as roofline denominators
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3
-# algorithmic FP32 operations per unit of work (the arithmetic of the definitions, not the
-# instructions the kernels issue)
-FLOP_PER_FP_SAMPLE = 7      # position fma (2), fraction (1), interpolation sub+fma (3), accumulate (1)
-FLOP_PER_FP_RAY = 2         # length scaling and residual subtraction
-FLOP_PER_BP_SAMPLE = 8      # position fma (2), fraction (1), 1-w (1), two weighted fma (4)
-FLOP_PER_BP_FINE_PIXEL = 2  # z = y_prev - scale * (U g)
-FLOP_PER_TV_PIXEL_ITER = 20
-FLOP_PER_TV_PIXEL_OUT = 8
+PEAK_FP32_TFLOPS = 157.3           # FP32 vector peak, counting packed FP32 (two lanes per operation)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # the same without packed FP32, which this build leaves out
+# algorithmic FP32 operations per unit of work: one Joseph sample (forward or back) is
+# 12 operations (position fma, floor, fraction, index, two taps, bounds mask and select,
+# interpolation sub + fma, accumulate); a TV-prox step is 30 operations per pixel
+# (divergence, gradient, magnitude with sqrt, reciprocal, normalisation)
+OPS_PER_SAMPLE = 12
+OPS_PER_FP_RAY = 2          # length scaling and residual subtraction
+OPS_PER_BP_FINE_PIXEL = 2   # z = y_prev - scale * (U g)
+OPS_PER_TV_PIXEL_ITER = 30
+OPS_PER_TV_PIXEL_OUT = 8    # final divergence, relaxation, momentum
 GATHER_BYTES_PER_SAMPLE = 8  # the two 4-byte interpolation taps of a Joseph sample
 KERNEL_DESCRIPTION = {"fp": "Joseph forward projection minus b", "bp": "matched gather back-projection fused with the "
                       "gradient step", "tv": "TV-prox with relaxation, momentum and pooling epilogue"}
@@ -102,6 +104,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the FP64 oracle timing")
     ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-PSNR comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice batched workload")
+    ap.add_argument("--no-diff", action="store_true",
+                    help="skip the differentiation workload (reverse mode through 10 unrolled iterations, 8 slices)")
     ap.add_argument("--no-scenarios", action="store_true",
                     help="skip the paper's three scenarios (sparse-view, low-dose, limited-angle)")
     ap.add_argument("--tune-cache", metavar="PATH",
@@ -126,6 +130,7 @@ def parse():
                          "per iteration group; with --trace-dir, VALU utilisation and L2 hit rate are derived")
     ap.add_argument("--trace-dir", help="with --pmc-summary: a kernel-trace directory for per-group durations")
     ap.add_argument("--cmd", default="", help="command line quoted in a summary")
+    ap.add_argument("--title", default="", help="with --trace-summary: the workload the trace covers")
     ap.add_argument("--bench-log", help="log of the profiled command (its JSON line is quoted in a trace summary)")
     return ap.parse_args()
 
@@ -206,13 +211,15 @@ def trace_summary(args) -> int:
     trace.sort(key=lambda r: int(r["Start_Timestamp"]))
     names = [_short(r["Kernel_Name"]) for r in trace]
     grids = [int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) for r in trace]
-    out = ["# rocprofv3 kernel trace: 512x512 multi-stage sketched PnP-SGD (720 views x 768 bins, f = 4, 2, 1, "
-           "1 of 8 view subsets)", "", "Command (repository root, one MI355X, library built):", "", "```",
-           args.cmd, "```", "", "Summary: `python bench.py --trace-summary <output dir> --cmd '<command>'"
+    title = args.title or ("512x512 multi-stage sketched PnP-SGD (720 views x 768 bins, f = 4, 2, 1, "
+                           "1 of 8 view subsets)")
+    out = [f"# rocprofv3 kernel trace: {title}", "", "Command (repository root, one MI355X, library built):", "",
+           "```", args.cmd, "```", "", "Summary: `python bench.py --trace-summary <output dir> --cmd '<command>'"
+           + (" --title '<workload>'" if args.title else "")
            + (" --bench-log <log>" if args.bench_log else "") + "`", "",
            "## Kernel statistics over the whole run (rocprofv3 --stats)", "",
            "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
-    for r in stats[:20]:
+    for r in stats[:30]:
         out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                    f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                    f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
@@ -220,8 +227,10 @@ def trace_summary(args) -> int:
     for g, j in label_dispatches(names, grids):
         groups.setdefault(g, []).append(j)
     n_rep = len(groups.get("tv_f1", [])) // 20 if groups else 0
-    out += ["", f"## Per iteration group, over {n_rep} complete replays of the schedule (graph and direct calls)", "",
-            "| group | kernel | launches | avg us | min us | max us | us per replay |", "|---|---|---|---|---|---|---|"]
+    if groups:
+        out += ["", f"## Per iteration group, over {n_rep} complete replays of the schedule (graph and direct calls)",
+                "", "| group | kernel | launches | avg us | min us | max us | us per replay |",
+                "|---|---|---|---|---|---|---|"]
     for g in sorted(groups, key=lambda k: (k.split("_f")[0], -int(k.split("_f")[1]))):
         d = [(int(trace[j]["End_Timestamp"]) - int(trace[j]["Start_Timestamp"])) / 1e3 for j in groups[g]]
         kn = sorted(set(names[j] for j in groups[g]))
@@ -475,9 +484,9 @@ def main() -> int:
         for t, (f, s, _a) in enumerate(sk_sched):
             smp = sum(vsamp[f][v] for v in sub_views[s])
             n_fine = npix
-            flops = {"fp": FLOP_PER_FP_SAMPLE * smp + FLOP_PER_FP_RAY * len(sub_views[s]) * B,
-                     "bp": FLOP_PER_BP_SAMPLE * smp + FLOP_PER_BP_FINE_PIXEL * n_fine,
-                     "tv": n_fine * (w.tv_iters * FLOP_PER_TV_PIXEL_ITER + FLOP_PER_TV_PIXEL_OUT)}
+            flops = {"fp": OPS_PER_SAMPLE * smp + OPS_PER_FP_RAY * len(sub_views[s]) * B,
+                     "bp": OPS_PER_SAMPLE * smp + OPS_PER_BP_FINE_PIXEL * n_fine,
+                     "tv": n_fine * (w.tv_iters * OPS_PER_TV_PIXEL_ITER + OPS_PER_TV_PIXEL_OUT)}
             for k, name in ((0, "fp"), (2, "bp"), (4, "tv")):
                 a_ = acc.setdefault((name, f), {"ms": 0.0, "n": 0, "flop": 0.0, "samples": 0, "pixel_views": 0})
                 a_["ms"] += evs[t][k].elapsed_time(evs[t][k + 1])
@@ -524,12 +533,18 @@ def main() -> int:
     roofline = {"kernel": f"{dom_name} ({KERNEL_DESCRIPTION[dom_name[:2]]}, pooling factor {dom_name[4:]})",
                 "bound": "alu", "achieved": round(dom["tflops"], 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(dom["tflops"] / PEAK_FP32_TFLOPS, 5), "traffic": traffic,
-                "traffic_source": traffic_src, "avg_launch_us": round(dom["avg_launch_us"], 3),
+                "traffic_source": traffic_src,
+                "ops_per_sample": OPS_PER_SAMPLE,
+                "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+                "frac_nonpacked": round(dom["tflops"] / PEAK_FP32_NONPACKED_TFLOPS, 5),
+                "avg_launch_us": round(dom["avg_launch_us"], 3),
                 "flop_per_launch": round(dom["flop_per_launch"]), "launches_timed": dom["launches_per_step"] * reps}
     if traffic:
         # the measured HBM rate of the dominant kernel and its share of the HBM roof
         hbm = traffic / (dom["avg_launch_us"] * 1e-6) / 1e12
         roofline.update(hbm_tb_per_s=round(hbm, 4), hbm_frac=round(hbm * 1e3 / PEAK_HBM_GBS, 5))
+    # the HBM bandwidth a plain device copy reaches on this GPU, beside the published figure
+    roofline.update(hbm_peak_spec_gb_per_s=PEAK_HBM_GBS, hbm_copy_measured_gb_per_s=round(copy_rate(torch), 1))
 
     # ---- time-to-PSNR: sketched vs full-gradient PnP-FISTA vs full-resolution PnP-SGD
     ttp = None
@@ -541,6 +556,11 @@ def main() -> int:
     bat = None
     if not args.no_batch:
         bat = batched_section(torch, fbpnp, synth, args.batch_steps, tune_cache)
+
+    # ---- the differentiation workload: reverse mode through unrolled iterations
+    diff = None
+    if not args.no_diff:
+        diff = differentiation_section(torch, fbpnp, synth)
 
     # ---- the paper's own experiment shapes: two-stage sketch against PnP-FISTA
     scen = None
@@ -579,11 +599,70 @@ def main() -> int:
                     for k, v in kernels.items()},
         "time_to_psnr": ttp,
         "batched": bat,
+        "differentiation": diff,
         "paper_scenarios": scen,
         "oracle_detail": odet,
     }
     print(json.dumps(result), flush=True)
     return 0
+
+
+def differentiation_section(torch, fbpnp, synth, reps=3):
+    """Reverse mode through 10 unrolled two-stage sketched iterations (5 at f = 2, then 5 at
+    f = 1, FISTA momentum, all views) on a batch of 8 slices of 512^2 with 360 views x 768
+    bins (seeded 20-ellipse phantoms, 1% Gaussian noise): the GPU time of the forward pass
+    (which keeps one checkpoint per iteration) and of the backward pass (gradients with
+    respect to the 8 initial images and the 10 step sizes), HIP events on the launch
+    stream around each pass as the API issues it, median over reps after a warm-up."""
+    from paper_2203_07308_amd.autograd import StepSpec, unrolled_pnp
+
+    n, V, nb, S, n2, n1 = 512, 360, 768, 8, 5, 5
+    gd = synth.fan_geometry(n, V, nb)
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [2, 1])
+    xts = np.stack([synth.rasterise(synth.random_ellipses(6000 + s, 20, n), n) for s in range(S)]).astype(np.float32)
+    xt_d = torch.from_numpy(xts).cuda()
+    ax = torch.empty((S, V * nb), device="cuda")
+    for s in range(S):
+        fbpnp.fanbeam_fp(plan, 1, xt_d[s].reshape(-1), ax[s])
+    ax_h = ax.cpu().numpy().astype(np.float64)
+    b_h = np.stack([synth.add_noise(ax_h[s], synth.standard_normal(6100 + s, ax_h[s].shape), "gaussian", 0.01)
+                    for s in range(S)]).astype(np.float32)
+    b = torch.from_numpy(b_h).cuda()
+    eta_k = [1.0 / fbpnp.power_lipschitz(plan, k, 100) for k in range(2)]
+    a = synth.momentum_table(n2 + n1)
+    specs = [StepSpec(0 if t < n2 else 1, a_t=float(a[t])) for t in range(n2 + n1)]
+    eta0 = torch.tensor([eta_k[0]] * n2 + [eta_k[1]] * n1, dtype=torch.float32, device="cuda")
+    x00 = (0.5 * xt_d + 0.05 * torch.from_numpy(np.random.default_rng(6200).random((S, n, n)).astype(np.float32))
+           .cuda()).contiguous()
+    fw, bw = [], []
+    for r in range(reps + 1):
+        x0 = x00.clone().requires_grad_(True)
+        eta = eta0.clone().requires_grad_(True)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        torch.cuda.synchronize()
+        e[0].record()
+        out = unrolled_pnp(plan, b, specs, x0, eta)
+        e[1].record()
+        loss = 0.5 * ((out - xt_d) ** 2).sum()
+        e[2].record()
+        loss.backward()
+        e[3].record()
+        torch.cuda.synchronize()
+        if r:
+            fw.append(e[0].elapsed_time(e[1]))
+            bw.append(e[2].elapsed_time(e[3]))
+    fms, bms = float(np.median(fw)), float(np.median(bw))
+    ok = bool(torch.isfinite(x0.grad).all()) and bool(torch.isfinite(eta.grad).all())
+    res = {"workload": "8 slices x 512^2, 360 views x 768 bins, 10 unrolled iterations (5 at f = 2, 5 at f = 1), "
+                       "all views, FISTA momentum, TV-prox 5 x lambda 0.01; loss 0.5 ||x_10 - x_true||^2",
+           "forward_ms": round(fms, 3), "backward_ms": round(bms, 3),
+           "backward_over_forward": round(bms / fms, 2),
+           "slice_iterations_per_s_forward": round(S * (n2 + n1) / (fms * 1e-3), 1),
+           "slice_iterations_per_s_forward_and_backward": round(S * (n2 + n1) / ((fms + bms) * 1e-3), 1),
+           "gradients_finite": ok}
+    log(f"differentiation: {res}")
+    plan.close()
+    return res
 
 
 def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x, y, xt, T, tune_cache):
@@ -948,6 +1027,14 @@ def cpu_baseline(synth, w, xt, sk_sched, eta, n_sub, budget_s=10.0):
                       f"(FP64 C oracle, OpenMP), {dt:.2f} s"}
 
 
+def copy_rate(torch, mib=512, reps=10):
+    """Device-to-device copy bandwidth (bytes read + bytes written per second, GB/s), median of reps."""
+    src = torch.ones(mib << 18, device="cuda")
+    dst = torch.empty_like(src)
+    ms = _gpu_ms(torch, lambda: dst.copy_(src), reps)
+    return 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
+
+
 def _gpu_ms(torch, fn, reps):
     """Median over reps of one call's duration on the current stream (HIP events), after a warm-up call."""
     fn()
@@ -963,41 +1050,48 @@ def _gpu_ms(torch, fn, reps):
 
 
 def oracle_detail(torch, fbpnp, synth, plan, s_full, xt, tune_cache):
-    """The FP64 oracle beside the GPU, on the host cores and on one thread: the full-view
-    forward and back projection of the 512^2 geometry at f = 1 (one call each), and the
-    complete 64^2 PnP-ISTA and 256^2 two-stage reconstructions (all host threads)."""
+    """The FP64 oracle beside the GPU, on all host threads and on one: full-view forward
+    and back projection of the three workload geometries (64^2, 256^2, 512^2) on their
+    f = 1, 2 and 4 grids (one call each; the GPU with its default launch configuration),
+    and the complete 64^2 PnP-ISTA and 256^2 two-stage reconstructions (all host threads)."""
     import oracle
 
     oracle.build(force=False)
-    w = synth.WORKLOADS["ms2g512"]
-    gd = w.geometry
-    og = oracle.Geometry(**gd)
-    V, B = gd["n_views"], gd["n_bins"]
-    samples = int(np.sum(plan.view_samples(s_full)))
-    x64 = xt.astype(np.float64)
-    y64 = np.random.default_rng(17).random((V, B))
     n_all = oracle.set_threads(0)
-    out = {"threads_all": n_all, "samples_full_projection": samples}
-    # GPU: the same full-view launches, configured for all views
-    plan.autotune(n_sel=V, cache_path=tune_cache)
-    xd = torch.from_numpy(xt.astype(np.float32)).cuda().reshape(-1)
-    yd = torch.from_numpy(y64.astype(np.float32)).cuda().reshape(-1)
-    ybuf = torch.empty(V * B, device="cuda")
-    xbuf = torch.empty(xd.numel(), device="cuda")
-    gpu = {"fp": _gpu_ms(torch, lambda: fbpnp.fanbeam_fp(plan, s_full, xd, ybuf), 20),
-           "bp": _gpu_ms(torch, lambda: fbpnp.fanbeam_bp(plan, s_full, yd, xbuf), 20)}
-    for name, fn in (("fp", lambda: oracle.fp(og, x64)), ("bp", lambda: oracle.bp(og, y64))):
-        d = {"gpu_ms": round(gpu[name], 4), "gpu_gsamples_per_s": round(samples / (gpu[name] * 1e-3) / 1e9, 2)}
-        for th in (n_all, 1):
-            oracle.set_threads(th)
-            t0 = time.time()
-            fn()
-            dt = time.time() - t0
-            d[f"oracle_s_{th}_threads"] = round(dt, 4)
-            d[f"oracle_gsamples_per_s_{th}_threads"] = round(samples / dt / 1e9, 4)
-        oracle.set_threads(n_all)
-        out[f"{name}_full_views_f1"] = d
-    log(f"oracle projectors: {out}")
+    out = {"threads_all": n_all, "projectors": {}}
+    for name in ("pnp64", "ms2g256", "ms2g512"):
+        wl = synth.WORKLOADS[name]
+        g2 = wl.geometry
+        og2 = oracle.Geometry(**g2)
+        V2, B2 = g2["n_views"], g2["n_bins"]
+        pl = fbpnp.Plan(fbpnp.Geometry(**g2), [1, 2, 4])
+        xt2 = synth.phantom(wl) if name != "ms2g512" else xt
+        y64 = np.random.default_rng(17).random((V2, B2))
+        yd = torch.from_numpy(y64.astype(np.float32)).cuda().reshape(-1)
+        ybuf = torch.empty(V2 * B2, device="cuda")
+        entry = {}
+        for k, f in enumerate((1, 2, 4)):
+            ny, nx = g2["ny"] // f, g2["nx"] // f
+            xs = np.asarray(xt2, dtype=np.float64).reshape(ny, f, nx, f).mean(axis=(1, 3))
+            xd = torch.from_numpy(xs.astype(np.float32)).cuda().reshape(-1)
+            xbuf = torch.empty(nx * ny, device="cuda")
+            smp = int(np.sum(pl.view_samples(k)))
+            d = {"grid": nx, "samples": smp,
+                 "gpu_fp_ms": round(_gpu_ms(torch, lambda: fbpnp.fanbeam_fp(pl, k, xd, ybuf), 20), 4),
+                 "gpu_bp_ms": round(_gpu_ms(torch, lambda: fbpnp.fanbeam_bp(pl, k, yd, xbuf), 20), 4)}
+            for op, fn in (("fp", lambda: oracle.fp(og2, xs, f)), ("bp", lambda: oracle.bp(og2, y64, f))):
+                for th in (n_all, 1):
+                    oracle.set_threads(th)
+                    t0 = time.time()
+                    fn()
+                    dt = time.time() - t0
+                    d[f"oracle_{op}_s_{th}_threads"] = round(dt, 4)
+                    d[f"oracle_{op}_gsamples_per_s_{th}_threads"] = round(smp / dt / 1e9, 4)
+                oracle.set_threads(n_all)
+            entry[f"f{f}"] = d
+        pl.close()
+        out["projectors"][name] = entry
+    log(f"oracle projectors: {out['projectors']}")
     # whole reconstructions of the two smaller workloads: GPU graph replay against the oracle
     loops = {}
     for name in ("pnp64", "ms2g256"):

@@ -25,6 +25,7 @@ struct BatchStage {
     const ViewRec* vrec;
     float* lines;  // x-major line image; the y-major one starts ly_off floats later
     int ly_off, line_bytes, pitch_x, pitch_y, nxs, nys, f;
+    int scatter_gap;  // the plan stage's scatter_gap
     float inv_ff;
 };
 

@@ -83,6 +83,21 @@ __global__ __launch_bounds__(64 * VG) void k_bp_batch(const SliceDesc* __restric
                                          D.nx, y_prev + D.img_off, D.zbuf);
 }
 
+template <int BB, int VG>
+__global__ __launch_bounds__(64 * VG) void k_bps_batch(const SliceDesc* __restrict__ desc,
+                                                       const uint32_t* __restrict__ items, int stage, int view0,
+                                                       int view_step, const float* __restrict__ eta, float sigma,
+                                                       const float* __restrict__ y_prev) {
+    const Item w = item_of(desc, items);
+    const SliceDesc& D = *w.d;
+    const BatchStage& S = D.st[stage];
+    const int n_sel = dcdiv(D.n_views, view_step);
+    const float scale = eta[w.d - desc] * sigma / (float)(S.f * S.f);
+    dev::bps_body<BB, VG, true>(w.local, S.rays, S.vrec, D.n_bins, nullptr, view0, view_step, n_sel, D.n_views,
+                                D.resid, S.nxs, S.nys, dcdiv(S.nxs, BB), S.scatter_gap, scale, nullptr, S.f, D.nx,
+                                y_prev + D.img_off, D.zbuf);
+}
+
 template <int T, int H, int NT>
 __global__ __launch_bounds__(NT) void k_tv_batch(const SliceDesc* __restrict__ desc,
                                                  const uint32_t* __restrict__ items, int next_stage, float lam,
@@ -149,7 +164,8 @@ fb_launch_config batch_config(const fb_batch* B, int stage, int n_sub) {
         long nblk = 0;
         for (const SliceDesc& D : B->h_desc) {
             const BatchStage& S = D.st[stage];
-            nblk += (long)cdiv(S.nxs, 8 * c.bp_px) * cdiv(S.nys, 8 * c.bp_px);
+            const int bw = bp_block_side(c.bp_px);
+            nblk += (long)cdiv(S.nxs, bw) * cdiv(S.nys, bw);
         }
         c.bp_vg = default_bp_vg(c.bp_px, nblk, nsel_min);
         if (c.bp_px == 4 && c.bp_vg > 4) c.bp_vg = 4;
@@ -160,7 +176,8 @@ fb_launch_config batch_config(const fb_batch* B, int stage, int n_sub) {
 
 // Work-item table of one launch kind: slices in longest-processing-time
 // order, each contributing its blocks in order. kind: 0 pooling, 1 forward
-// projection (param = fp_seg), 2 backprojection (param = bp_px), 3 TV (param =
+// projection (param = fp_seg), 2 backprojection (param = bp_px, whose block side
+// is bp_block_side(bp_px)), 3 TV (param =
 // tile side). Tables are built by set-up calls (batch creation, configuration
 // changes, fb_batch_prepare, the autotuner, graph creation); a step only looks
 // them up, so it never allocates or synchronises.
@@ -193,11 +210,13 @@ static fb_status work_items(fb_batch* B, int kind, int stage, int param, int n_s
                 cost[i] = std::max(S.nxs, S.nys);
                 break;
             }
-            case 2:
-                // a block gathers every selected view over its pixel square
-                blocks[i] = (long)cdiv(S.nxs, 8 * param) * cdiv(S.nys, 8 * param);
+            case 2: {
+                // a block takes every selected view over its pixel square
+                const int bw = bp_block_side(param);
+                blocks[i] = (long)cdiv(S.nxs, bw) * cdiv(S.nys, bw);
                 cost[i] = (long)ns * S.f;
                 break;
+            }
             default:
                 blocks[i] = (long)cdiv(D.nx, param) * cdiv(D.ny, param);
                 cost[i] = 1;
@@ -236,12 +255,12 @@ fb_status launch_fp_batch(fb_batch* B, int stage, int n_sub, int subset, const f
     return check_launch("batched fp");
 }
 
-// A slice whose back-projection blocks (8 px stage pixels) reach the source
+// A slice whose back-projection blocks (bp_block_side(px) stage pixels) reach the source
 // circle: the whole batch's back-projection at that stage takes every bin of a
 // view as a candidate, with one pixel per lane.
 static bool batch_all_bins(const fb_batch* B, int stage, int px) {
     for (const fb_plan* p : B->plans)
-        if (bp_blocks_reach_source(p->g, p->stages[stage], 8 * px)) return true;
+        if (bp_blocks_reach_source(p->g, p->stages[stage], bp_block_side(px))) return true;
     return false;
 }
 
@@ -268,7 +287,22 @@ fb_status launch_bp_batch(fb_batch* B, int stage, int n_sub, int subset, const f
         case 8: FB_BPB(8, PX); break;  \
         default: FB_BPB(16, PX); break; \
     }
-    if (px == 4) {
+#define FB_BPSB(BB, VG)                                                                                          \
+    FB_BLAUNCH((k_bps_batch<BB, VG>), dim3(t->n), dim3(64 * VG), s, B->d_desc, t->d, stage, subset, n_sub, eta, sigma, \
+               y_prev)
+#define FB_BPSB_VG(BB)                  \
+    switch (vg) {                       \
+        case 1: FB_BPSB(BB, 1); break;  \
+        case 2: FB_BPSB(BB, 2); break;  \
+        case 4: FB_BPSB(BB, 4); break;  \
+        case 8: FB_BPSB(BB, 8); break;  \
+        default: FB_BPSB(BB, 16); break; \
+    }
+    if (px == 32) {
+        FB_BPSB_VG(32)
+    } else if (px == 16) {
+        FB_BPSB_VG(16)
+    } else if (px == 4) {
         switch (vg) {
             case 1: FB_BPB(1, 4); break;
             case 2: FB_BPB(2, 4); break;
@@ -279,6 +313,8 @@ fb_status launch_bp_batch(fb_batch* B, int stage, int n_sub, int subset, const f
     } else {
         FB_BPB_VG(1)
     }
+#undef FB_BPSB_VG
+#undef FB_BPSB
 #undef FB_BPB_VG
 #undef FB_BPB
     return check_launch("batched bp");
@@ -392,6 +428,7 @@ fb_status fb_batch_create(const fb_geom* geoms, int n_slices, int n_stages, cons
             b.nxs = S.nxs;
             b.nys = S.nys;
             b.f = S.f;
+            b.scatter_gap = S.scatter_gap;
             b.inv_ff = 1.f / (float)(S.f * S.f);
         }
         B->h_desc.push_back(D);

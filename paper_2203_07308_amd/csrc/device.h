@@ -334,22 +334,21 @@ __device__ __forceinline__ bool bp_fine_pixel(int e, int bw, int bx, int by, int
     return by * bw + cr < nys && bx * bw + cc < nxs;
 }
 
-template <int VG, int PX, bool kFused>
-__device__ __forceinline__ void bp_finish(const float (*__restrict__ red)[PX * PX][64], int bx, int by, int nxs,
-                                          int nys, float scale, float* __restrict__ xo, int f, int nx,
-                                          const float* __restrict__ yprev, float* __restrict__ z,
-                                          const float* __restrict__ mu, float mu_scale,
-                                          float* __restrict__ g_out) {
-    constexpr int BW = 8 * PX, NT = 64 * VG;
+// The block's epilogue, NT threads, one output value per thread and pass;
+// gval(cr, cc) is the block's gradient value at stage pixel (cr, cc) of the
+// block (its parts already added in a fixed order).
+template <int BW, int NT, bool kFused, typename GVal>
+__device__ __forceinline__ void bp_epilogue(const GVal& gval, int bx, int by, int nxs, int nys, float scale,
+                                            float* __restrict__ xo, int f, int nx, const float* __restrict__ yprev,
+                                            float* __restrict__ z, const float* __restrict__ mu, float mu_scale,
+                                            float* __restrict__ g_out) {
     const int ff = kFused ? f : 1;
     const int n = BW * BW * ff * ff;
     const float rf = 1.f / (float)ff, rfw = 1.f / (float)(BW * ff);
     for (int e = threadIdx.x; e < n; e += NT) {
         int cr, cc, FR, FC;
         if (!bp_fine_pixel(e, BW, bx, by, nxs, nys, ff, rf, rfw, cr, cc, FR, FC)) continue;
-        const int lane = ((cr / PX) << 3) | (cc / PX), slot = (cr % PX) * PX + (cc % PX);
-        float g = red[0][slot][lane];
-        for (int w = 1; w < VG; ++w) g += red[w][slot][lane];
+        const float g = gval(cr, cc);
         const size_t q = (size_t)(by * BW + cr) * nxs + bx * BW + cc;
         if (!kFused) {
             xo[q] = scale * g;
@@ -360,6 +359,21 @@ __device__ __forceinline__ void bp_finish(const float (*__restrict__ red)[PX * P
         const float ms = mu ? mu_scale * mu[q] : 0.f;
         z[(size_t)FR * nx + FC] = fmaf(-scale, g, yp - ms);
     }
+}
+
+template <int VG, int PX, bool kFused>
+__device__ __forceinline__ void bp_finish(const float (*__restrict__ red)[PX * PX][64], int bx, int by, int nxs,
+                                          int nys, float scale, float* __restrict__ xo, int f, int nx,
+                                          const float* __restrict__ yprev, float* __restrict__ z,
+                                          const float* __restrict__ mu, float mu_scale,
+                                          float* __restrict__ g_out) {
+    auto gval = [&](int cr, int cc) {
+        const int lane = ((cr / PX) << 3) | (cc / PX), slot = (cr % PX) * PX + (cc % PX);
+        float g = red[0][slot][lane];
+        for (int w = 1; w < VG; ++w) g += red[w][slot][lane];
+        return g;
+    };
+    bp_epilogue<8 * PX, 64 * VG, kFused>(gval, bx, by, nxs, nys, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
 }
 
 // Work-group blk (64 VG threads) of a backprojection; views as in fp_body.
@@ -466,6 +480,216 @@ __device__ __forceinline__ void bp_body(int blk, const RayRec* __restrict__ rays
         for (int b = 0; b < PX; ++b) red[wave][a * PX + b][lane] = acc[a][b];
     __syncthreads();
     bp_finish<VG, PX, kFused>(red, bx, by, nxs, nys, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
+}
+
+// ---------------------------------------------------------------------------
+// Matched backprojection, scatter form.
+//
+// A work-group owns a B x B block of stage pixels (B = 16 or 32); each of its
+// VG wavefronts takes every VG-th selected view (as bp_body does) and adds
+// that view's samples into its own LDS copy of the block, grown by two guard
+// cells on every side. For the rays of one dominance class in the block's
+// footprint, lane (slot s, offset q) handles line q of the block (column
+// C0 + q for x-major rays, row R0 + q for y-major ones); the S = 64 / B slots
+// take S equal parts of the class's bin range and walk them in step, one ray
+// each per iteration, with k_fp's float operations:
+//   p = fma(kf, dpos, pos_c), kf = line - nlines/2 (centred position),
+//   cell floor(p) += (1 - fract(p)) y len,  cell floor(p) + 1 += fract(p) y len.
+// The additions are plain LDS reads and writes (LDS float atomics serialise
+// lane by lane on this GPU). They are race-free because the rays of one
+// iteration never share a cell: the plan gives, per stage, the smallest bin
+// distance `gap` at which two rays of one class and view lie at least two
+// cells apart on every line of the grid, and the slots run in step only when
+// their parts are at least that long (else slot 0 takes the whole range). A
+// position outside the block is clamped so that both taps fall in the guard
+// cells, which are never read (the slots may collide only there, or on lines
+// outside the grid, whose cells are never read either).
+// Ray records reach the lanes through registers: in a round, lane (row rho, k)
+// holds ray k of its slot's part, and iteration t broadcasts lane t of every
+// row of 16 lanes (DPP row_newbcast).
+// The wavefronts' copies are added in wavefront order at the end, so results
+// are bitwise reproducible run to run.
+// ---------------------------------------------------------------------------
+template <int B>
+struct ScatterTile {
+    static constexpr int S = 64 / B;  // slots of B lanes
+    static constexpr int P = B + 5;   // row pitch (odd)
+    static constexpr int CELLS = (B + 4) * P;  // the block with two guard cells on each side
+};
+
+// Lane t of each row of 16 lanes, broadcast to its row.
+template <int T>
+__device__ __forceinline__ float row_bcast(float v) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x150 + T, 0xF, 0xF, true));
+}
+
+// Iteration T of a round: the slot rays held by lane T of each row add their
+// sample on this lane's line. A: accumulator stride of the position axis (P
+// for x-major rays, whose positions are rows; 1 for y-major ones); cq:
+// accumulator index of position 0 on this lane's line.
+template <int A, int T>
+__device__ __forceinline__ void bps_sample(float pc, float dp, float yl, float kf, float lo, float hi, int cq,
+                                           float* __restrict__ acc) {
+    const float p = fmaf(kf, row_bcast<T>(dp), row_bcast<T>(pc));
+    const float q = __builtin_amdgcn_fmed3f(p, lo, hi);
+    const float w = __builtin_amdgcn_fractf(q);
+    const int fl = (int)floorf(q);
+    const int e = (A == 1 ? fl : __mul24(fl, A)) + cq;
+    const float yy = row_bcast<T>(yl);
+    const float wy = w * yy;
+    const float c0 = acc[e], c1 = acc[e + A];
+    acc[e] = c0 + (yy - wy);
+    acc[e + A] = c1 + wy;
+}
+
+// Iterations T0 .. of a round, in groups of four without branches (so one
+// iteration's arithmetic can overlap the previous one's LDS round trip),
+// until tn iterations are done; lanes past the round's rays hold a position
+// far outside, whose taps fall in the guard cells.
+template <int A, int T0 = 0>
+__device__ __forceinline__ void bps_round(int tn, float pc, float dp, float yl, float kf, float lo, float hi,
+                                          int cq, float* __restrict__ acc) {
+    if constexpr (T0 < 16) {
+        bps_sample<A, T0>(pc, dp, yl, kf, lo, hi, cq, acc);
+        bps_sample<A, T0 + 1>(pc, dp, yl, kf, lo, hi, cq, acc);
+        bps_sample<A, T0 + 2>(pc, dp, yl, kf, lo, hi, cq, acc);
+        bps_sample<A, T0 + 3>(pc, dp, yl, kf, lo, hi, cq, acc);
+        if (T0 + 4 >= tn) return;
+        bps_round<A, T0 + 4>(tn, pc, dp, yl, kf, lo, hi, cq, acc);
+    }
+}
+
+// A round's ray records for this lane: ray first + r0 + k of its slot's part,
+// if that lies in the part (L rays) and in the range (up to b); else a
+// position far outside with no weight. The loads take no branch (a lane
+// without a ray reads bin a of the range), so waiting for one round's records
+// can leave the next round's in flight.
+__device__ __forceinline__ void bps_fetch(const RayRec* __restrict__ rv, const float* __restrict__ yv, int a,
+                                          int first, int r0, int k, int L, int b, bool mine, float& pc, float& dp,
+                                          float& len, float& res) {
+    const int j = first + r0 + k;
+    const bool ok = mine && r0 + k < L && j <= b;
+    const int jj = ok ? j : a;
+    const RayRec q = rv[jj];
+    const float yq = yv[jj];
+    pc = ok ? q.pos_c : -1e30f;
+    dp = ok ? q.dpos : 0.f;
+    len = ok ? q.len : 0.f;
+    res = ok ? yq : 0.f;
+}
+
+// The rays a .. b of one class of one view: S parts of L rays walked in step
+// (one part, slot 0's, when the parts would be shorter than gap), in rounds
+// of 16, each round's records loaded during the previous round.
+template <int B, int A>
+__device__ __forceinline__ void bps_class(const RayRec* __restrict__ rv, const float* __restrict__ yv, int a, int b,
+                                          int gap, int slot, int k, float kf, float lo, float hi, int cq,
+                                          float* __restrict__ acc) {
+    constexpr int S = ScatterTile<B>::S;
+    const int n = b - a + 1;
+    if (n <= 0) return;
+    int L = (n + S - 1) / S;
+    const bool parts = L >= gap;
+    if (!parts) L = n;
+    const int first = a + (parts ? slot * L : 0);
+    const bool mine = parts || slot == 0;
+    float pc0, dp0, len0, res0, pc1, dp1, len1, res1;
+    bps_fetch(rv, yv, a, first, 0, k, L, b, mine, pc0, dp0, len0, res0);
+    for (int r0 = 0; r0 < L; r0 += 32) {
+        bps_fetch(rv, yv, a, first, r0 + 16, k, L, b, mine, pc1, dp1, len1, res1);
+        bps_round<A>(min(16, L - r0), pc0, dp0, res0 * len0, kf, lo, hi, cq, acc);
+        if (r0 + 16 >= L) break;
+        bps_fetch(rv, yv, a, first, r0 + 32, k, L, b, mine, pc0, dp0, len0, res0);
+        bps_round<A>(min(16, L - r0 - 16), pc1, dp1, res1 * len1, kf, lo, hi, cq, acc);
+    }
+}
+
+// Work-group blk (64 VG threads) of a scatter-form backprojection; arguments
+// and results as bp_body's (blocks_x counts B-wide blocks), plus the stage's
+// slot gap (Stage::scatter_gap). Stages whose blocks reach the source circle
+// take bp_body's every-bin form instead.
+template <int B, int VG, bool kFused>
+__device__ __forceinline__ void bps_body(int blk, const RayRec* __restrict__ rays, const ViewRec* __restrict__ vrec,
+                                         int n_bins, const int32_t* __restrict__ views, int view0, int view_step,
+                                         int n_sel, int n_views, const float* __restrict__ y, int nxs, int nys,
+                                         int blocks_x, int gap, float scale, float* __restrict__ xo, int f,
+                                         int nx, const float* __restrict__ yprev, float* __restrict__ z,
+                                         const float* __restrict__ mu = nullptr, float mu_scale = 0.f,
+                                         float* __restrict__ g_out = nullptr) {
+    using Tl = ScatterTile<B>;
+    constexpr int P = Tl::P;
+    __shared__ float accs[VG * Tl::CELLS];
+    // (the wavefront index is uniform: read it as such, so loops over its views
+    // and rounds stay scalar)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int bx = blk % blocks_x, by = blk / blocks_x;
+    const int C0 = bx * B, R0 = by * B;
+    float* const acc = accs + wave * Tl::CELLS;
+    // the wavefront's own copy; its LDS accesses complete in order, so no barrier
+    for (int e = lane; e < Tl::CELLS; e += 64) acc[e] = 0.f;
+    const int q = lane % B;
+    const int mid_r = nys >> 1, mid_c = nxs >> 1;
+    // x-major rays: lines are columns C0 + q, positions are rows
+    const float kfx = (float)(C0 + q - mid_c);
+    const float lox = (float)(R0 - mid_r - 2), hix = (float)(R0 - mid_r + B);
+    const int cqx = (mid_r - R0 + 2) * P + q + 2;
+    // y-major rays: lines are rows R0 + q, positions are columns
+    const float kfy = (float)(R0 + q - mid_r);
+    const float loy = (float)(C0 - mid_c - 2), hiy = (float)(C0 - mid_c + B);
+    const int cqy = (q + 2) * P + mid_c - C0 + 2;
+    // this lane's slot, and the ray of its slot's part it holds in a round
+    const int slot = lane / B, k = lane & 15;
+    // corners of the block grown by one pixel on each side (a ray reaches a
+    // pixel when its position lies within one pixel of it)
+    const float hx = 0.5f * (float)(nxs - 1), hy = 0.5f * (float)(nys - 1);
+    const float cb0 = (float)(C0 - 1) - hx, cb1 = (float)(C0 + B) - hx;
+    const float rb0 = (float)(R0 - 1) - hy, rb1 = (float)(R0 + B) - hy;
+    const int n_mine = n_sel > wave ? (n_sel - wave + VG - 1) / VG : 0;
+    for (int t0 = 0; t0 < n_mine; t0 += 64) {
+        // lane u: view t0 + u of this wavefront, its selection row and the
+        // footprint's bins of each class
+        int my_v = -1, my_i = 0, xa = 0, xb = -1, ya = 0, yb = -1;
+        if (t0 + lane < n_mine) {
+            const int iu = wave + VG * (t0 + lane);
+            const int vu = views ? views[iu] : view0 + iu * view_step;
+            if ((unsigned)vu < (unsigned)n_views) {  // invalid view index: no contribution
+                const ViewRec vq = vrec[vu];
+                const float q0 = proj_bin(vq, cb0, rb0), q1 = proj_bin(vq, cb1, rb0);
+                const float q2 = proj_bin(vq, cb0, rb1), q3 = proj_bin(vq, cb1, rb1);
+                const float jmin = fminf(fminf(q0, q1), fminf(q2, q3));
+                const float jmax = fmaxf(fmaxf(q0, q1), fmaxf(q2, q3));
+                const int j0 = (int)fmaxf(floorf(jmin - kProjEps), 0.f);
+                const int j1 = (int)fminf(ceilf(jmax + kProjEps), (float)(n_bins - 1));
+                my_v = vu;
+                my_i = iu;
+                xa = max(vq.xlo, j0);
+                xb = min(vq.xhi, j1);
+                ya = max(vq.ylo, j0);
+                yb = min(vq.yhi, j1);
+            }
+        }
+        const int tn = min(64, n_mine - t0);
+        for (int u = 0; u < tn; ++u) {
+            const int v = __builtin_amdgcn_readlane(my_v, u);
+            if (v < 0) continue;
+            const int i = __builtin_amdgcn_readlane(my_i, u);
+            const RayRec* rv = rays + (size_t)v * n_bins;
+            const float* yv = y + (size_t)i * n_bins;
+            bps_class<B, P>(rv, yv, __builtin_amdgcn_readlane(xa, u), __builtin_amdgcn_readlane(xb, u), gap, slot, k,
+                            kfx, lox, hix, cqx, acc);
+            bps_class<B, 1>(rv, yv, __builtin_amdgcn_readlane(ya, u), __builtin_amdgcn_readlane(yb, u), gap, slot, k,
+                            kfy, loy, hiy, cqy, acc);
+        }
+    }
+    __syncthreads();
+    auto gval = [&](int cr, int cc) {
+        const int e = (cr + 2) * P + cc + 2;
+        float g = accs[e];
+        for (int w = 1; w < VG; ++w) g += accs[w * Tl::CELLS + e];
+        return g;
+    };
+    bp_epilogue<B, 64 * VG, kFused>(gval, bx, by, nxs, nys, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
 }
 
 // ---------------------------------------------------------------------------

@@ -52,6 +52,9 @@ struct Stage {
     RayRec* rays = nullptr;         // device [n_views][n_bins]
     ViewRec* vrec = nullptr;        // device [n_views]
     int pitch_x = 0, pitch_y = 0;   // line pitches of the two line images
+    // smallest bin distance at which two rays of one class and one view lie at
+    // least two cells apart on every line of the grid (scatter backprojector)
+    int scatter_gap = 1 << 30;
 };
 
 }  // namespace fbpnp
@@ -104,6 +107,8 @@ fb_status hip_fail(hipError_t e, const char* what);
 fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays, std::vector<ViewRec>& views,
                              std::vector<int64_t>& view_samples);
 fb_status validate_geometry(const fb_geom& g);
+// Stage::scatter_gap of a stage's ray and view tables.
+int scatter_gap(const fb_geom& g, int f, const std::vector<RayRec>& rays, const std::vector<ViewRec>& views);
 // Bicubic sketch table of one axis (n pixels, factor f): S (n / f rows) or its
 // adjoint S^T (n rows), each row a window of `taps` consecutive inputs.
 fb_status bicubic_axis_tables(int n, int f, bool adjoint, std::vector<int>& lo, std::vector<float>& w, int& taps);
@@ -190,6 +195,9 @@ fb_status capture_graph(const std::function<fb_status(hipStream_t)>& body, fb_gr
 // Launch configurations: defaults, validation, and a plan stage's effective one.
 int default_fp_seg(long waves1);
 int default_bp_px(long npx);
+// Side of a backprojection block in stage pixels: 8 bp_px for the gather form
+// (bp_px = 1, 2, 4 pixels per lane), bp_px itself for the scatter form (16, 32).
+int bp_block_side(int bp_px);
 int default_bp_vg(int px, long nblk, int n_sel);
 int default_tv_tile(long tiles32);
 // True when the back-projector's pixel blocks of bw stage pixels, grown by the

@@ -63,6 +63,18 @@ __global__ __launch_bounds__(64 * VG) void k_bp(const RayRec* __restrict__ rays,
                                            blocks_x, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
 }
 
+template <int B, int VG, bool kFused>
+__global__ __launch_bounds__(64 * VG) void k_bps(const RayRec* __restrict__ rays, const ViewRec* __restrict__ vrec,
+                                                 int n_bins, const int32_t* __restrict__ views, int view0,
+                                                 int view_step, int n_sel, int n_views, const float* __restrict__ y,
+                                                 int nxs, int nys, int blocks_x, int gap, float scale,
+                                                 float* __restrict__ xo, int f, int nx, const float* __restrict__ yprev,
+                                                 float* __restrict__ z, const float* __restrict__ mu, float mu_scale,
+                                                 float* __restrict__ g_out) {
+    dev::bps_body<B, VG, kFused>(blockIdx.x, rays, vrec, n_bins, views, view0, view_step, n_sel, n_views, y, nxs, nys,
+                                 blocks_x, gap, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
+}
+
 template <int T, int H, int NT>
 __global__ __launch_bounds__(NT) void k_tv(const float* __restrict__ z, int nx, int ny, float lam, float tau,
                                            int n_iter, const float* __restrict__ p_in, float* __restrict__ p_out,
@@ -231,6 +243,7 @@ int default_bp_vg(int px, long nblk, int n_sel) {
     return vg;
 }
 int default_tv_tile(long tiles32) { return tiles32 < 256 ? 16 : 32; }
+int bp_block_side(int bp_px) { return bp_px >= 16 ? bp_px : 8 * bp_px; }
 
 bool bp_blocks_reach_source(const fb_geom& g, const Stage& st, int bw) {
     // the union of the blocks grown by one pixel on each side, in centred
@@ -249,7 +262,8 @@ fb_status check_config(const fb_launch_config& c) {
         return false;
     };
     if (!in(c.fp_seg, {1, 2, 4, 8})) return fail(FB_EINVAL, "launch config: fp_seg must be 0, 1, 2, 4 or 8");
-    if (!in(c.bp_px, {1, 2, 4})) return fail(FB_EINVAL, "launch config: bp_px must be 0, 1, 2 or 4");
+    if (!in(c.bp_px, {1, 2, 4, 16, 32}))
+        return fail(FB_EINVAL, "launch config: bp_px must be 0, 1, 2, 4 (gather) or 16, 32 (scatter)");
     if (!in(c.bp_vg, {1, 2, 4, 8, 16})) return fail(FB_EINVAL, "launch config: bp_vg must be 0, 1, 2, 4, 8 or 16");
     if (c.bp_px == 4 && c.bp_vg > 4) return fail(FB_EINVAL, "launch config: bp_px = 4 allows bp_vg <= 4");
     if (!in(c.tv_tile, {16, 32})) return fail(FB_EINVAL, "launch config: tv_tile must be 0, 16 or 32");
@@ -262,7 +276,7 @@ fb_launch_config plan_config(const fb_plan* p, int stage, int n_sel) {
     if (!c.fp_seg) c.fp_seg = default_fp_seg((long)n_sel * cdiv(p->g.n_bins, 64));
     if (!c.bp_px) c.bp_px = default_bp_px((long)st.nxs * st.nys);
     if (!c.bp_vg) {
-        const int bw = 8 * c.bp_px;
+        const int bw = bp_block_side(c.bp_px);
         c.bp_vg = default_bp_vg(c.bp_px, (long)cdiv(st.nxs, bw) * cdiv(st.nys, bw), n_sel);
         if (c.bp_px == 4 && c.bp_vg > 4) c.bp_vg = 4;
     }
@@ -306,14 +320,36 @@ static fb_status launch_bp_t(const fb_plan* p, int stage, const float* y, const 
     const int n_sel = sel.n;
     const fb_launch_config c = plan_config(p, stage, n_sel);
     // blocks that reach the source circle: every bin a candidate, one pixel per lane
-    const bool all_bins = bp_blocks_reach_source(p->g, st, 8 * c.bp_px);
+    const bool all_bins = bp_blocks_reach_source(p->g, st, bp_block_side(c.bp_px));
     const int px = all_bins ? 1 : c.bp_px, vg = c.bp_vg;
-    const int bw = 8 * px;
+    const int bw = bp_block_side(px);
     const int bxs = cdiv(st.nxs, bw), bys = cdiv(st.nys, bw), nblk = bxs * bys;
     const int nb = p->g.n_bins, f = st.f, nx = p->g.nx;
     if (all_bins) {
         FB_LAUNCH((k_bp<4, 1, kFused, true>), dim3(nblk), dim3(256), s, st.rays, st.vrec, nb, sel.list, sel.view0, sel.step, n_sel,
                   p->g.n_views, y, st.nxs, st.nys, bxs, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
+        return check_launch("fanbeam_bp");
+    }
+    if (px >= 16) {
+#define FB_BPS(BB, VG)                                                                                         \
+    FB_LAUNCH((k_bps<BB, VG, kFused>), dim3(nblk), dim3(64 * VG), s, st.rays, st.vrec, nb, sel.list, sel.view0, \
+              sel.step, n_sel, p->g.n_views, y, st.nxs, st.nys, bxs, st.scatter_gap, scale, xo, f, nx, yprev, z, mu, \
+              mu_scale, g_out)
+#define FB_BPS_VG(BB)                  \
+    switch (vg) {                      \
+        case 1: FB_BPS(BB, 1); break;  \
+        case 2: FB_BPS(BB, 2); break;  \
+        case 4: FB_BPS(BB, 4); break;  \
+        case 8: FB_BPS(BB, 8); break;  \
+        default: FB_BPS(BB, 16); break; \
+    }
+        if (px == 32) {
+            FB_BPS_VG(32)
+        } else {
+            FB_BPS_VG(16)
+        }
+#undef FB_BPS_VG
+#undef FB_BPS
         return check_launch("fanbeam_bp");
     }
 #define FB_BP(VG, PX)                                                                                         \
@@ -435,6 +471,7 @@ fb_status fb_plan_create(const fb_geom* geom, int n_stages, const int32_t* facto
         std::vector<ViewRec> vr;
         st = build_stage_tables(*geom, S.f, rays, vr, S.view_samples);
         if (st != FB_OK) return cleanup(st);
+        S.scatter_gap = scatter_gap(*geom, S.f, rays, vr);
         for (int64_t n : S.view_samples) S.samples += n;
         if (hipMalloc(&S.rays, rays.size() * sizeof(RayRec)) != hipSuccess ||
             hipMalloc(&S.vrec, vr.size() * sizeof(ViewRec)) != hipSuccess) {

@@ -184,6 +184,38 @@ fb_status build_stage_tables(const fb_geom& g, int f, std::vector<RayRec>& rays,
     return FB_OK;
 }
 
+// Adjacent rays j, j+1 of one dominance class and one view cross every line
+// of the grid in the same order, so the distance between rays j and j+m on a
+// line is at least m times the smallest adjacent distance dmin, and the
+// distance is linear along the lines (smallest at the first or last line). The
+// kernels evaluate positions in float (error far below 0.05 cells at these
+// sizes), so m >= 2.05 / dmin keeps two such rays at least two cells apart,
+// which the scatter backprojector needs to add their taps without a race.
+int scatter_gap(const fb_geom& g, int f, const std::vector<RayRec>& rays, const std::vector<ViewRec>& views) {
+    const int nxs = g.nx / f, nys = g.ny / f, nb = g.n_bins;
+    double dmin = HUGE_VAL;
+    for (int k = 0; k < g.n_views; ++k) {
+        const ViewRec& v = views[k];
+        for (int cls = 0; cls < 2; ++cls) {
+            const int lo = cls ? v.ylo : v.xlo, hi = cls ? v.yhi : v.xhi;
+            const int nlines = cls ? nys : nxs, lmid = nlines / 2;
+            for (int j = lo; j < hi; ++j) {
+                const RayRec& a = rays[(size_t)k * nb + j];
+                const RayRec& b = rays[(size_t)k * nb + j + 1];
+                for (int l : {0, nlines - 1}) {
+                    const double t = (double)(l - lmid);
+                    const double d = std::fabs(((double)b.pos_c + t * (double)b.dpos) -
+                                               ((double)a.pos_c + t * (double)a.dpos));
+                    dmin = std::min(dmin, d);
+                }
+            }
+        }
+    }
+    if (!(dmin > 0.0)) return 1 << 30;  // (no adjacent pair: any gap will do; a zero distance: one part)
+    const double m = std::ceil(2.05 / dmin);
+    return m >= (double)(1 << 30) ? 1 << 30 : std::max(1, (int)m);
+}
+
 // ---------------------------------------------------------------------------
 // Bicubic sketch tables (Sec. 3: resizing with bicubic interpolation).
 // Output o of an axis of n pixels reduced by f sits at input coordinate

@@ -207,9 +207,14 @@ void cache_put(const char* path, const std::string& key, const fb_launch_config&
 
 std::vector<std::pair<int, int>> bp_candidates(int n_sel_min) {
     std::vector<std::pair<int, int>> c;
+    // gather form: pixels per lane 1, 2, 4
     for (int px : {1, 2, 4})
         for (int vg : {1, 2, 4, 8, 16})
             if ((px < 4 || vg <= 4) && vg <= std::max(1, n_sel_min)) c.push_back({px, vg});
+    // scatter form: block sides 16 and 32 (it pays only with several wavefronts per block)
+    for (int b : {16, 32})
+        for (int vg : {4, 8, 16})
+            if (vg <= std::max(1, n_sel_min)) c.push_back({b, vg});
     return c;
 }
 

@@ -149,6 +149,26 @@ def test_batched_slices_equal_single_slice_runs():
         np.testing.assert_array_equal(host(batch.image(x, i)), ref)
 
 
+def test_batched_scatter_form_equals_single_slice_runs():
+    """The scatter back-projector in a batched launch, bit for bit the same slice run alone."""
+    gds, batch, xts, bs, b_arena = make_batch(seed=70)
+    sched = schedule()
+    eta = etas(batch, gds)
+    forms = [dict(fp_seg=0, bp_px=16, bp_vg=4, tv_tile=0), dict(fp_seg=0, bp_px=32, bp_vg=8, tv_tile=0)]
+    for k in range(len(FACTORS)):
+        batch.set_config(k, forms[k % len(forms)])
+    say("batched scatter", [(g["nx"], g["n_views"]) for g in gds])
+    x = run_batched(batch, b_arena, sched, eta)
+    xg = run_batched(batch, b_arena, sched, eta, graph=True)
+    np.testing.assert_array_equal(host(x), host(xg))
+    cfgs = [batch.get_config(k, 3 if k == 0 else 1) for k in range(len(FACTORS))]
+    assert all(c["bp_px"] in (16, 32) for c in cfgs)
+    for i, g in enumerate(gds):
+        say("single slice, scatter", i)
+        ref = run_single(g, bs[i], sched, eta[:, i], cfgs)
+        np.testing.assert_array_equal(host(batch.image(x, i)), ref)
+
+
 def test_batched_graph_equals_direct_calls():
     gds, batch, xts, bs, b_arena = make_batch(seed=60)
     sched = schedule(4, 2, 4)
@@ -306,7 +326,7 @@ def test_batched_slice_matches_oracle_loop():
 def candidate_configs():
     out = []
     for seg in (1, 2, 4, 8):
-        for px, vg in ((1, 1), (1, 4), (2, 2), (2, 16), (4, 1), (4, 4)):
+        for px, vg in ((1, 1), (1, 4), (2, 2), (2, 16), (4, 1), (4, 4), (16, 4), (32, 16)):
             for tile in (16, 32):
                 out.append(dict(fp_seg=seg, bp_px=px, bp_vg=vg, tv_tile=tile))
     return out
@@ -334,7 +354,7 @@ def test_batched_autotuner_candidates_agree_and_cache(tmp_path):
     lines = cache.read_text().splitlines()
     assert len(lines) == len(FACTORS)
     for c in tuned:
-        assert c["fp_seg"] in (1, 2, 4, 8) and c["bp_px"] in (1, 2, 4) and c["tv_tile"] in (16, 32)
+        assert c["fp_seg"] in (1, 2, 4, 8) and c["bp_px"] in (1, 2, 4, 16, 32) and c["tv_tile"] in (16, 32)
     got = host(run_batched(batch, b_arena, sched, eta))
     assert rel(got, base) <= 1e-5
     # a second batch of the same slices takes the cached choice (no new cache lines)

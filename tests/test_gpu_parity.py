@@ -130,8 +130,10 @@ def test_fanbeam_fp_matches_oracle(name, f, sel):
             assert np.all(got[i] == 0)
 
 
-# backprojector launch shapes: the built-in choice and each pixel block size
-BP_FORMS = [dict(), dict(bp_px=1, bp_vg=16), dict(bp_px=2, bp_vg=4), dict(bp_px=4, bp_vg=1)]
+# backprojector launch shapes: the built-in choice, each pixel block size of the gather form
+# and each block side of the scatter form
+BP_FORMS = [dict(), dict(bp_px=1, bp_vg=16), dict(bp_px=2, bp_vg=4), dict(bp_px=4, bp_vg=1),
+            dict(bp_px=16, bp_vg=4), dict(bp_px=32, bp_vg=16), dict(bp_px=32, bp_vg=1)]
 
 
 @pytest.mark.parametrize("name,f,sel", FP_CASES)
@@ -509,6 +511,24 @@ def test_loop_ms2g512_subsets_multistage(tmp_path):
     say("loop ms2g512 tuned", [plan.get_config(k, gd["n_views"] // 8) for k in range(3)])
     x = run_gpu(plan, gd, b, sched_g, eta, a)
     assert rel(x, ref) <= 1e-4, rel(x, ref)
+
+
+def test_loop_ms2g256_two_stage_scatter_backprojection():
+    """The 256^2 two-stage loop with the scatter back-projector at both stages (block sides 16
+    and 32), direct and as a graph, against the oracle's loop."""
+    w, gd, og, xt, b = problem("ms2g256")
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [2, 1])
+    plan.set_config(0, dict(fp_seg=0, bp_px=16, bp_vg=16, tv_tile=0))
+    plan.set_config(1, dict(fp_seg=0, bp_px=32, bp_vg=16, tv_tile=0))
+    L2, L1 = oracle.power_lipschitz(og, 2, 60), oracle.power_lipschitz(og, 1, 60)
+    eta = np.array([1 / L2] * 30 + [1 / L1] * 20)
+    a = synth.momentum_table(50)
+    sched_g = [(0, None, 1.0)] * 30 + [(1, None, 1.0)] * 20
+    say("loop ms2g256 scatter")
+    x = run_gpu(plan, gd, b, sched_g, eta, a)
+    ref = oracle.pnp_run(og, b.astype(np.float64), [(2, None, 1.0)] * 30 + [(1, None, 1.0)] * 20, eta, a)
+    assert rel(x, ref) <= 1e-4, rel(x, ref)
+    np.testing.assert_array_equal(run_gpu(plan, gd, b, sched_g, eta, a, graph=True), x)
 
 
 def test_loop_widefan_two_stage_subsets():
