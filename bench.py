@@ -131,6 +131,13 @@ def parse():
     ap.add_argument("--trace-dir", help="with --pmc-summary: a kernel-trace directory for per-group durations")
     ap.add_argument("--cmd", default="", help="command line quoted in a summary")
     ap.add_argument("--title", default="", help="with --trace-summary: the workload the trace covers")
+    ap.add_argument("--forms", action="store_true",
+                    help="launch every forward-projector and back-projector form of each stage of the 512^2 "
+                         "workload (one 90-view subset) and of the 256^2 sparse-view scenario, ten times each, "
+                         "printing a label per form; run under rocprofv3 --kernel-trace and summarise with "
+                         "--forms-summary (no JSON line)")
+    ap.add_argument("--forms-summary", nargs=2, metavar=("TRACE_DIR", "LOG"),
+                    help="kernel durations per form from a rocprofv3 kernel trace of --forms and its log (no GPU use)")
     ap.add_argument("--bench-log", help="log of the profiled command (its JSON line is quoted in a trace summary)")
     return ap.parse_args()
 
@@ -348,10 +355,100 @@ def counter_tables(args):
     return out
 
 
+FORM_REPS = 10
+
+
+def projector_forms(torch, fbpnp, synth) -> int:
+    """Every launch form of the projector (lanes per ray; taps from global memory or LDS
+    where the stage fits) and of the back-projector (gather with 1, 2, 4 pixels per lane;
+    scatter over 16 and 32 pixel blocks; 4, 8, 16 wavefronts per block) at each stage of
+    the 512^2 workload (subset 0 of 8: 90 views) and of the 256^2 sparse-view scenario (90
+    views), FORM_REPS launches each, after one label line per form."""
+    cases = [("ms2g512", synth.WORKLOADS["ms2g512"].geometry, 8),
+             ("sparse_view", synth.SCENARIOS["sparse_view"].geometry, 1)]
+    for name, gd, n_sub in cases:
+        V, nb = gd["n_views"], gd["n_bins"]
+        plan = fbpnp.Plan(fbpnp.Geometry(**gd), [4, 2, 1])
+        views = torch.from_numpy(synth.subset_views(0, n_sub, V).astype(np.int32)).cuda()
+        n_sel = views.numel()
+        yb = torch.rand(n_sel * nb, device="cuda")
+        for k, f in enumerate((4, 2, 1)):
+            ny, nx = plan.coarse_shape(k)
+            xs = torch.rand((ny, nx), device="cuda")
+            y = torch.empty(n_sel * nb, device="cuda")
+            forms = [("fp", dict(fp_seg=seg, fp_lds=lds)) for lds in (1, 2) for seg in (1, 2, 4, 8)]
+            forms += [("bp", dict(bp_px=px, bp_vg=vg)) for px in (1, 2, 4, 16, 32) for vg in (4, 8, 16)
+                      if not (px == 4 and vg > 4)]
+            for kind, cfg in forms:
+                try:
+                    plan.set_config(k, cfg)
+                except fbpnp.FbError:
+                    continue
+                print(f"form {name} f={f} {kind} " + " ".join(f"{a}={b}" for a, b in cfg.items()), flush=True)
+                for _ in range(FORM_REPS):
+                    if kind == "fp":
+                        fbpnp.fanbeam_fp(plan, k, xs, y, views)
+                    else:
+                        fbpnp.fanbeam_bp(plan, k, yb, xs, views)
+                torch.cuda.synchronize()
+            plan.set_config(k, None)
+        plan.close()
+    # the floor of a dependent kernel: a captured graph of 256 one-element kernels, each
+    # depending on the one before, replayed 20 times (HIP events)
+    t = torch.zeros(1, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        t.add_(1.0)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(256):
+                t.add_(1.0)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    with Events(torch) as ev:
+        for _ in range(20):
+            g.replay()
+    print(f"floor {1e3 * ev.ms / (20 * 256):.2f} us per dependent one-element kernel in a graph", flush=True)
+    return 0
+
+
+def forms_summary(args) -> int:
+    trace_dir, log_path = args.forms_summary
+    trace = _csv(trace_dir, "kernel_trace.csv")
+    trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+    proj = [r for r in trace if _short(r["Kernel_Name"]).startswith(("k_fp", "k_bp"))]
+    labels = [ln.split(None, 1)[1].strip() for ln in open(log_path) if ln.startswith("form ")]
+    out = ["# rocprofv3 kernel trace: every projector and back-projector form, per stage", "",
+           "Workloads: the 512x512 geometry (720 views x 768 bins) with one 90-view subset, and the 256x256 "
+           "sparse-view scenario (90 views x 228 bins); stages f = 4, 2, 1; all-view selections as view lists.", "",
+           "Command (repository root, one MI355X, library built):", "", "```", args.cmd, "```", "",
+           "Summary: `python bench.py --forms-summary <trace dir> <log> --cmd '<command>'`", "",
+           f"Average kernel duration over the last {FORM_REPS - 2} of {FORM_REPS} launches of each form.", "",
+           "| workload | stage | kind | form | kernel | avg us |", "|---|---|---|---|---|---|"]
+    if len(proj) != FORM_REPS * len(labels):
+        raise SystemExit(f"{len(proj)} projector dispatches for {len(labels)} forms")
+    for i, lab in enumerate(labels):
+        grp = proj[FORM_REPS * i:FORM_REPS * (i + 1)]
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in grp[2:]]
+        name, stage, kind, *cfg = lab.split()
+        out.append(f"| {name} | {stage} | {kind} | {' '.join(cfg)} | `{_short(grp[0]['Kernel_Name'])}` | "
+                   f"{sum(d) / len(d):.2f} |")
+    floor = [ln.strip() for ln in open(log_path) if ln.startswith("floor ")]
+    if floor:
+        out += ["", f"Kernel floor measured in the same run: {floor[-1][6:]}."]
+    print("\n".join(out))
+    return 0
+
+
 def main() -> int:
     args = parse()
     if args.trace_summary:
         return trace_summary(args)
+    if args.forms_summary:
+        return forms_summary(args)
     if args.pmc_summary:
         return pmc_summary(args)
     if args.gpus != 1:
@@ -365,6 +462,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.forms:
+        return projector_forms(torch, fbpnp, synth)
     w = synth.WORKLOADS["ms2g512"]
     gd = w.geometry
     V, B, N = gd["n_views"], gd["n_bins"], gd["nx"]

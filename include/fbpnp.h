@@ -132,17 +132,23 @@ fb_status fb_plan_sketch_up(const fb_plan* plan, int stage, const float* v, floa
  * the split changes a summation order):
  *   fp_seg   lanes per ray in the forward projector (1, 2, 4 or 8; a
  *            wavefront holds 64 / fp_seg rays, a work-group 256 / fp_seg)
- *   bp_px    pixels per lane side in the backprojector (1, 2 or 4; a
- *            wavefront owns an 8 bp_px square)
+ *   bp_px    backprojector form and block: 1, 2 or 4 selects the gather form
+ *            with bp_px x bp_px pixels per lane (a wavefront owns an 8 bp_px
+ *            square); 16 or 32 the scatter form over bp_px x bp_px blocks
  *   bp_vg    wavefronts per work-group splitting the views (1..16, <= 4 when
  *            bp_px = 4)
  *   tv_tile  TV-prox output tile side (16 or 32)
+ *   fp_lds   where the forward projector reads its taps: 1 from the stage's
+ *            line images in global memory, 2 from a copy of them in LDS
+ *            (only for stages whose two line images fit, at most 147456
+ *            bytes, e.g. grids up to 128 x 128; fb_plan_set_config refuses
+ *            2 for other stages; batches take 1)
  * A zero field selects the built-in default for the call's size.
  * fb_plan_set_config: cfg NULL restores every default.
  * fb_plan_get_config: the configuration calls with n_sel views use.
  */
 typedef struct fb_launch_config {
-    int32_t fp_seg, bp_px, bp_vg, tv_tile;
+    int32_t fp_seg, bp_px, bp_vg, tv_tile, fp_lds;
 } fb_launch_config;
 fb_status fb_plan_set_config(fb_plan* plan, int stage, const fb_launch_config* cfg);
 fb_status fb_plan_get_config(const fb_plan* plan, int stage, int n_sel, fb_launch_config* out);

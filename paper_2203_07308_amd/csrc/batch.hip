@@ -171,6 +171,7 @@ fb_launch_config batch_config(const fb_batch* B, int stage, int n_sub) {
         if (c.bp_px == 4 && c.bp_vg > 4) c.bp_vg = 4;
     }
     if (!c.tv_tile) c.tv_tile = default_tv_tile(tiles32);
+    if (!c.fp_lds) c.fp_lds = 1;
     return c;
 }
 
@@ -395,7 +396,7 @@ fb_status fb_batch_create(const fb_geom* geoms, int n_slices, int n_stages, cons
     fb_batch* B = new fb_batch();
     B->n_stages = n_stages;
     B->factors.assign(factors, factors + n_stages);
-    B->cfg.assign(n_stages, fb_launch_config{0, 0, 0, 0});
+    B->cfg.assign(n_stages, fb_launch_config{0, 0, 0, 0, 0});
     int64_t io = 0, so = 0;
     for (int i = 0; i < n_slices; ++i) {
         fb_plan* p = nullptr;
@@ -483,9 +484,10 @@ fb_status fb_batch_slice_plan(fb_batch* B, int slice, fb_plan** out) {
 
 fb_status fb_batch_set_config(fb_batch* B, int stage, const fb_launch_config* cfg) {
     if (!B || stage < 0 || stage >= B->n_stages) return fail(FB_EINVAL, "fb_batch_set_config: bad arguments");
-    const fb_launch_config c = cfg ? *cfg : fb_launch_config{0, 0, 0, 0};
+    const fb_launch_config c = cfg ? *cfg : fb_launch_config{0, 0, 0, 0, 0};
     fb_status st = check_config(c);
     if (st != FB_OK) return st;
+    if (c.fp_lds == 2) return fail(FB_EINVAL, "launch config: batches read projector taps from global memory");
     const fb_launch_config old = B->cfg[stage];
     B->cfg[stage] = c;
     for (int n_sub : std::set<int>(B->prepared))

@@ -32,6 +32,17 @@ namespace dev {
 // ---------------------------------------------------------------------------
 constexpr int kTile = 32;
 
+// Work-groups are handed to the GPU's 8 XCDs (each with its own L2) in turn by
+// launch index. Launch index id of n work-groups of a spatial launch gets tile
+// xcd_tile(id, n): XCD k = id mod 8 takes the k-th of 8 consecutive runs of
+// tiles (tiles are row-major), so the back-projector blocks that write z and
+// y_t of a band of image rows and the denoiser tiles that read them run on
+// the same XCD and find them in its L2.
+__device__ __forceinline__ int xcd_tile(int id, int n) {
+    const int q = n >> 3, r = n & 7, k = id & 7, j = id >> 3;
+    return k * q + min(k, r) + j;
+}
+
 // Sum of an F x F block of an image with row pitch S (global memory or LDS),
 // added from zero in row order; all F^2 reads are issued before the sum.
 template <int F>
@@ -111,28 +122,47 @@ __device__ __forceinline__ T lane_pair(T v, int o) {
     return __builtin_bit_cast(T, r);
 }
 
-// Work-group blk (256 threads) of a projection; view i of the selection is
-// views[i], or view0 + i * view_step without a list.
-// proj_out (optional): the projection itself, before b is subtracted, stored
-// by view ([n_views][n_bins]).
-template <bool kResid, int SEG>
-__device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays, int n_bins, int bins_padded,
-                                        const int32_t* __restrict__ views, int view0, int view_step, int n_sel,
-                                        int n_views, const float* __restrict__ lines, int ly_off, int line_bytes,
-                                        int pitch_x, int pitch_y, int nxs, int nys, const float* __restrict__ b,
-                                        float* __restrict__ y, float* __restrict__ proj_out = nullptr) {
+// The two interpolation taps at byte offset off of the stage's line images:
+// from global memory (through a buffer resource over both images, so a load
+// outside them would return zero instead of faulting) or from a copy of the
+// images in LDS.
+struct TapsGlobal {
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ TapsGlobal(const float* lines, int line_bytes)
+        : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(lines), (short)0, line_bytes, kBufWord3)) {}
+    __device__ __forceinline__ void operator()(int off, float& a, float& c) const {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0);
+        a = __uint_as_float(t[0]);
+        c = __uint_as_float(t[1]);
+    }
+};
+struct TapsLds {
+    const float* lds;
+    __device__ __forceinline__ void operator()(int off, float& a, float& c) const {
+        const float* q = lds + (off >> 2);
+        a = q[0];
+        c = q[1];
+    }
+};
+
+// Projection work of 256 threads (local thread index tid), block blk of the
+// launch's rays; view i of the selection is views[i], or view0 + i * view_step
+// without a list. proj_out (optional): the projection itself, before b is
+// subtracted, stored by view ([n_views][n_bins]).
+template <bool kResid, int SEG, typename Taps>
+__device__ __forceinline__ void fp_block(int blk, int tid, const Taps& taps, const RayRec* __restrict__ rays,
+                                         int n_bins, int bins_padded, const int32_t* __restrict__ views, int view0,
+                                         int view_step, int n_sel, int n_views, int ly_off, int pitch_x, int pitch_y,
+                                         int nxs, int nys, const float* __restrict__ b, float* __restrict__ y,
+                                         float* __restrict__ proj_out) {
     constexpr int R = 64 / SEG;  // rays per wavefront; SEG lanes share one ray
-    const int lane = threadIdx.x & 63;
-    const int wave = (blk * 256 + (int)threadIdx.x) >> 6;
+    const int lane = tid & 63;
+    const int wave = (blk * 256 + tid) >> 6;
     const int waves_per_view = bins_padded / R;
     const int i = wave / waves_per_view;
     const int j = (wave - i * waves_per_view) * R + lane % R;
     const int seg = lane / R;
     const bool active = i < n_sel && j < n_bins;
-    // both line images of the stage as one buffer: 32-bit offsets, and a load
-    // outside it would return zero instead of faulting
-    const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(lines), (short)0, line_bytes, kBufWord3);
     int v = 0;
     if (active) v = views ? views[i] : view0 + i * view_step;
     const bool valid = active && (unsigned)v < (unsigned)n_views;  // invalid view index: a zero row
@@ -180,8 +210,8 @@ __device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays
             const float p = __builtin_amdgcn_fmed3f(fmaf(kf, r.dpos, r.pos_c), plo, phi);
             const float w = __builtin_amdgcn_fractf(p);
             const int i0 = (int)floorf(p);
-            const auto t = __builtin_amdgcn_raw_buffer_load_b64(rsrc, off + i0 * 4, 0, 0);
-            const float a = __uint_as_float(t[0]), c = __uint_as_float(t[1]);
+            float a, c;
+            taps(off + i0 * 4, a, c);
             acc += fmaf(w, c - a, a);
             kf += 1.f;
             off += step;
@@ -200,6 +230,39 @@ __device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays
         }
         y[(size_t)i * n_bins + j] = val;
     }
+}
+
+// Work-group blk (256 threads) of a projection with its taps from global memory.
+template <bool kResid, int SEG>
+__device__ __forceinline__ void fp_body(int blk, const RayRec* __restrict__ rays, int n_bins, int bins_padded,
+                                        const int32_t* __restrict__ views, int view0, int view_step, int n_sel,
+                                        int n_views, const float* __restrict__ lines, int ly_off, int line_bytes,
+                                        int pitch_x, int pitch_y, int nxs, int nys, const float* __restrict__ b,
+                                        float* __restrict__ y, float* __restrict__ proj_out = nullptr) {
+    fp_block<kResid, SEG>(blk, (int)threadIdx.x, TapsGlobal(lines, line_bytes), rays, n_bins, bins_padded, views,
+                          view0, view_step, n_sel, n_views, ly_off, pitch_x, pitch_y, nxs, nys, b, y, proj_out);
+}
+
+// Projection with the stage's two line images staged in LDS (lds_floats of
+// them, copied by the whole work-group), for stages small enough to fit:
+// every 256-thread quarter of the work-group then takes blocks q + 4
+// gridDim.x k of the launch's rays, reading its taps from LDS.
+template <bool kResid, int SEG>
+__device__ __forceinline__ void fp_body_lds(float* __restrict__ lds, int lds_floats, int n_blocks,
+                                            const RayRec* __restrict__ rays, int n_bins, int bins_padded,
+                                            const int32_t* __restrict__ views, int view0, int view_step, int n_sel,
+                                            int n_views, const float* __restrict__ lines, int ly_off, int pitch_x,
+                                            int pitch_y, int nxs, int nys, const float* __restrict__ b,
+                                            float* __restrict__ y, float* __restrict__ proj_out) {
+    const float4* src = reinterpret_cast<const float4*>(lines);
+    float4* dst = reinterpret_cast<float4*>(lds);
+    for (int e = threadIdx.x; e < (lds_floats >> 2); e += blockDim.x) dst[e] = src[e];
+    __syncthreads();
+    const TapsLds taps{lds};
+    const int quarter = threadIdx.x >> 8, tid = threadIdx.x & 255;
+    for (int blk = blockIdx.x * 4 + quarter; blk < n_blocks; blk += gridDim.x * 4)
+        fp_block<kResid, SEG>(blk, tid, taps, rays, n_bins, bins_padded, views, view0, view_step, n_sel, n_views,
+                              ly_off, pitch_x, pitch_y, nxs, nys, b, y, proj_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -768,12 +831,10 @@ __device__ __forceinline__ void tv_body(int bx, int by, const float* __restrict_
         p2b[k] = (inb && p_in) ? p_in[plane + gi + nx] : 0.f;
         zla[k] = za[k] * il;
         zlb[k] = zb[k] * il;
-        // output cells of the tile; their x_prev is fetched now, used at the end
+        // output cells of the tile
         const bool col_out = lc >= H && lc < H + T && gc < nx;
         out0[k] = live[k] && col_out && lr >= H && lr < H + T && gr < ny;
         out1[k] = live[k] && col_out && lr + 1 >= H && lr + 1 < H + T && gr + 1 < ny;
-        xpa[k] = (out0[k] && mode == 1 && !p_out) ? x_prev[gi] : 0.f;
-        xpb[k] = (out1[k] && mode == 1 && !p_out) ? x_prev[gi + nx] : 0.f;
         if (live[k]) {
             sp1[e + S] = p1b[k];
             sp2[e] = p2a[k];
@@ -781,6 +842,21 @@ __device__ __forceinline__ void tv_body(int bx, int by, const float* __restrict_
         }
     }
     __syncthreads();
+    // x_prev of the output cells, used only at the end: fetched now, after the
+    // wait for the loads above, so that its latency overlaps the dual steps
+    // (every lane loads, from cell 0 where its cell is no output cell, whose
+    // value the epilogue never uses; so the loads take no branch and nothing
+    // waits for them before the epilogue)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) xpa[k] = xpb[k] = 0.f;
+    __builtin_amdgcn_s_waitcnt(0);  // the loads above are complete on every path
+    if (mode == 1 && !p_out) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            xpa[k] = x_prev[out0[k] ? ga[k] : 0];
+            xpb[k] = x_prev[out1[k] ? ga[k] + nx : 0];
+        }
+    }
     for (int it = 0; it < n_iter; ++it) {
         float ua[NP], ub[NP];
 #pragma unroll

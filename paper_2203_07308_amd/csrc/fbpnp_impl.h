@@ -198,6 +198,8 @@ int default_bp_px(long npx);
 // Side of a backprojection block in stage pixels: 8 bp_px for the gather form
 // (bp_px = 1, 2, 4 pixels per lane), bp_px itself for the scatter form (16, 32).
 int bp_block_side(int bp_px);
+// Whether a stage's two line images fit in the LDS-staged forward projector.
+bool fp_lds_fits(const fb_plan* p, int stage);
 int default_bp_vg(int px, long nblk, int n_sel);
 int default_tv_tile(long tiles32);
 // True when the back-projector's pixel blocks of bw stage pixels, grown by the

@@ -58,9 +58,26 @@ __global__ __launch_bounds__(64 * VG) void k_bp(const RayRec* __restrict__ rays,
                                                 const float* __restrict__ yprev, float* __restrict__ z,
                                                 const float* __restrict__ mu, float mu_scale,
                                                 float* __restrict__ g_out) {
-    dev::bp_body<VG, PX, kFused, kAllBins>(blockIdx.x, rays, vrec, n_bins, views, view0, view_step, n_sel, n_views, y,
+    dev::bp_body<VG, PX, kFused, kAllBins>(dev::xcd_tile(blockIdx.x, gridDim.x), rays, vrec, n_bins, views, view0,
+                                           view_step, n_sel, n_views, y,
                                            nxs, nys,
                                            blocks_x, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
+}
+
+// The line images of a stage small enough to stage in LDS (floats).
+constexpr int kFpLdsFloats = 36864;
+
+template <bool kResid, int SEG>
+__global__ __launch_bounds__(1024) void k_fp_lds(int lds_floats, int n_blocks, const RayRec* __restrict__ rays,
+                                                 int n_bins, int bins_padded, const int32_t* __restrict__ views,
+                                                 int view0, int view_step, int n_sel, int n_views,
+                                                 const float* __restrict__ lines, int ly_off, int pitch_x,
+                                                 int pitch_y, int nxs, int nys, const float* __restrict__ b,
+                                                 float* __restrict__ y, float* __restrict__ proj_out) {
+    __shared__ float stage_lines_lds[kFpLdsFloats];
+    dev::fp_body_lds<kResid, SEG>(stage_lines_lds, lds_floats, n_blocks, rays, n_bins, bins_padded, views, view0,
+                                  view_step, n_sel, n_views, lines, ly_off, pitch_x, pitch_y, nxs, nys, b, y,
+                                  proj_out);
 }
 
 template <int B, int VG, bool kFused>
@@ -71,7 +88,8 @@ __global__ __launch_bounds__(64 * VG) void k_bps(const RayRec* __restrict__ rays
                                                  float* __restrict__ xo, int f, int nx, const float* __restrict__ yprev,
                                                  float* __restrict__ z, const float* __restrict__ mu, float mu_scale,
                                                  float* __restrict__ g_out) {
-    dev::bps_body<B, VG, kFused>(blockIdx.x, rays, vrec, n_bins, views, view0, view_step, n_sel, n_views, y, nxs, nys,
+    dev::bps_body<B, VG, kFused>(dev::xcd_tile(blockIdx.x, gridDim.x), rays, vrec, n_bins, views, view0, view_step,
+                                 n_sel, n_views, y, nxs, nys,
                                  blocks_x, gap, scale, xo, f, nx, yprev, z, mu, mu_scale, g_out);
 }
 
@@ -82,7 +100,9 @@ __global__ __launch_bounds__(NT) void k_tv(const float* __restrict__ z, int nx, 
                                            float* __restrict__ x_out, float* __restrict__ y_out,
                                            float* __restrict__ hist, int pf, float pinv, float* __restrict__ plx,
                                            int ppx, float* __restrict__ ply, int ppy, int pnxs, int pnys) {
-    dev::tv_body<T, H, NT>(blockIdx.x, blockIdx.y, z, nx, ny, lam, tau, n_iter, p_in, p_out, mode, alpha, a_t, x_prev,
+    const int tile = dev::xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    dev::tv_body<T, H, NT>(tile % gridDim.x, tile / gridDim.x, z, nx, ny, lam, tau, n_iter, p_in, p_out, mode, alpha,
+                           a_t, x_prev,
                            x_out, y_out, hist, pf, pinv, plx, ppx, ply, ppy, pnxs, pnys);
 }
 
@@ -267,6 +287,7 @@ fb_status check_config(const fb_launch_config& c) {
     if (!in(c.bp_vg, {1, 2, 4, 8, 16})) return fail(FB_EINVAL, "launch config: bp_vg must be 0, 1, 2, 4, 8 or 16");
     if (c.bp_px == 4 && c.bp_vg > 4) return fail(FB_EINVAL, "launch config: bp_px = 4 allows bp_vg <= 4");
     if (!in(c.tv_tile, {16, 32})) return fail(FB_EINVAL, "launch config: tv_tile must be 0, 16 or 32");
+    if (!in(c.fp_lds, {1, 2})) return fail(FB_EINVAL, "launch config: fp_lds must be 0, 1 or 2");
     return FB_OK;
 }
 
@@ -281,7 +302,28 @@ fb_launch_config plan_config(const fb_plan* p, int stage, int n_sel) {
         if (c.bp_px == 4 && c.bp_vg > 4) c.bp_vg = 4;
     }
     if (!c.tv_tile) c.tv_tile = default_tv_tile((long)cdiv(p->g.nx, 32) * cdiv(p->g.ny, 32));
+    if (!c.fp_lds) c.fp_lds = 1;
     return c;
+}
+
+bool fp_lds_fits(const fb_plan* p, int stage) {
+    const Stage& st = p->stages[stage];
+    return (long)st.nxs * st.pitch_x + (long)st.nys * st.pitch_y <= kFpLdsFloats;
+}
+
+// work-groups of an LDS-staged projection: one per compute unit at most, each
+// taking four blocks of 256 threads at a time
+static int cu_count() {
+    static int n = 0;
+    if (!n) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            n = v;
+        else
+            n = 256;
+    }
+    return n;
 }
 
 fb_status launch_fp(const fb_plan* p, int stage, bool resid, const ViewSel& sel, const float* b, float* y,
@@ -290,10 +332,32 @@ fb_status launch_fp(const fb_plan* p, int stage, bool resid, const ViewSel& sel,
     const Stage& st = p->stages[stage];
     StageLines L = stage_lines(p, stage);
     const int nb = p->g.n_bins;
-    const int seg = plan_config(p, stage, n_sel).fp_seg;
+    const fb_launch_config c = plan_config(p, stage, n_sel);
+    const int seg = c.fp_seg;
     const int rays_per_wave = 64 / seg;
     const int bp = cdiv(nb, rays_per_wave) * rays_per_wave;
     const int blocks = cdiv(n_sel * (bp / rays_per_wave), 4);
+    if (c.fp_lds == 2 && fp_lds_fits(p, stage)) {
+        const int lds_floats = st.nxs * st.pitch_x + st.nys * st.pitch_y;
+        const int grid = std::min(cdiv(blocks, 4), cu_count());
+#define FB_FPL(RES, SG)                                                                                         \
+    FB_LAUNCH((k_fp_lds<RES, SG>), dim3(grid), dim3(1024), s, lds_floats, blocks, st.rays, nb, bp, sel.list,      \
+              sel.view0, sel.step, n_sel, p->g.n_views, L.lx, L.ly_off, st.pitch_x, st.pitch_y, st.nxs, st.nys, b, \
+              y, proj_out)
+        if (resid) {
+            if (seg == 8) FB_FPL(true, 8);
+            else if (seg == 4) FB_FPL(true, 4);
+            else if (seg == 2) FB_FPL(true, 2);
+            else FB_FPL(true, 1);
+        } else {
+            if (seg == 8) FB_FPL(false, 8);
+            else if (seg == 4) FB_FPL(false, 4);
+            else if (seg == 2) FB_FPL(false, 2);
+            else FB_FPL(false, 1);
+        }
+#undef FB_FPL
+        return check_launch("fanbeam_fp");
+    }
 #define FB_FP(RES, SG)                                                                                        \
     FB_LAUNCH((k_fp<RES, SG>), dim3(blocks), dim3(256), s, st.rays, nb, bp, sel.list, sel.view0, sel.step,      \
               n_sel, p->g.n_views, L.lx,                                                                      \
@@ -459,7 +523,7 @@ fb_status fb_plan_create(const fb_geom* geom, int n_stages, const int32_t* facto
         return code;
     };
     size_t line_floats = 0;
-    p->cfg.assign(n_stages, fb_launch_config{0, 0, 0, 0});
+    p->cfg.assign(n_stages, fb_launch_config{0, 0, 0, 0, 0});
     for (int s = 0; s < n_stages; ++s) {
         Stage S;
         S.f = factors[s];
@@ -530,8 +594,10 @@ fb_status fb_plan_stage_info(const fb_plan* p, int stage, fb_stage_info* out) {
 fb_status fb_plan_set_config(fb_plan* p, int stage, const fb_launch_config* cfg) {
     fb_status st = check_stage(p, stage);
     if (st != FB_OK) return st;
-    const fb_launch_config c = cfg ? *cfg : fb_launch_config{0, 0, 0, 0};
+    const fb_launch_config c = cfg ? *cfg : fb_launch_config{0, 0, 0, 0, 0};
     if ((st = check_config(c)) != FB_OK) return st;
+    if (c.fp_lds == 2 && !fp_lds_fits(p, stage))
+        return fail(FB_EINVAL, "launch config: the stage's line images do not fit in LDS (fp_lds = 2)");
     p->cfg[stage] = c;
     return FB_OK;
 }

@@ -1,13 +1,14 @@
 // Autotuner for the launch configurations of plans and batches.
 //
 // For every stage it times each candidate (lanes per ray of the forward
-// projector, pixels per lane and view-splitting wavefronts of the
-// backprojector, TV tile) on synthetic data of the stage's real shape with
+// projector and where it reads its taps, the backprojector's form, block and
+// view-splitting wavefronts, TV tile) on synthetic data of the stage's real shape with
 // HIP events, keeps the fastest candidate whose output agrees with the default
 // configuration's (relative L2 difference at most 1e-5; candidates differ only
 // in summation order), and stores it in the plan or batch. Results are cached
 // in a text file, one line per (device, geometry, stage, view selection):
-//   <key> <fp_seg> <bp_px> <bp_vg> <tv_tile>
+//   <key> <fp_seg> <bp_px> <bp_vg> <tv_tile> <fp_lds>
+// (a line without fp_lds reads as fp_lds = 1).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -191,9 +192,12 @@ bool cache_get(const char* path, const std::string& key, fb_launch_config* c) {
         std::string k;
         fb_launch_config v{};
         if (ls >> k >> v.fp_seg >> v.bp_px >> v.bp_vg >> v.tv_tile && k == key && v.fp_seg && v.bp_px && v.bp_vg &&
-            v.tv_tile && check_config(v) == FB_OK) {
-            *c = v;
-            found = true;
+            v.tv_tile) {
+            if (!(ls >> v.fp_lds)) v.fp_lds = 1;  // lines written before the field existed
+            if (check_config(v) == FB_OK && v.fp_lds) {
+                *c = v;
+                found = true;
+            }
         }
     }
     return found;
@@ -202,7 +206,7 @@ bool cache_get(const char* path, const std::string& key, fb_launch_config* c) {
 void cache_put(const char* path, const std::string& key, const fb_launch_config& c) {
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << " " << c.fp_seg << " " << c.bp_px << " " << c.bp_vg << " " << c.tv_tile << "\n";
+    out << key << " " << c.fp_seg << " " << c.bp_px << " " << c.bp_vg << " " << c.tv_tile << " " << c.fp_lds << "\n";
 }
 
 std::vector<std::pair<int, int>> bp_candidates(int n_sel_min) {
@@ -279,23 +283,27 @@ static fb_status autotune_plan(fb_plan* p, int n_sel, const char* cache_path, hi
             (st = need(out, npix, "the denoised image")) != FB_OK || (st = need(xprev, npix, "x_prev")) != FB_OK ||
             (st = need(views, (size_t)n_sel, "the view list")) != FB_OK)
             return st;
-        p->cfg[k] = fb_launch_config{0, 0, 0, 0};
+        p->cfg[k] = fb_launch_config{0, 0, 0, 0, 0};
         const fb_launch_config def = plan_config(p, k, n_sel);
         if ((st = launch_prepare(p, k, img.f(), nx, S.f, s)) != FB_OK) return st;
-        // forward projection (residual form, as in the iteration)
-        std::vector<int> segs = {def.fp_seg};
-        for (int v : {1, 2, 4, 8})
-            if (v != def.fp_seg) segs.push_back(v);
-        int seg = def.fp_seg;
-        st = pick<int>(
-            segs,
-            [&](const int& c) {
-                p->cfg[k].fp_seg = c;
+        // forward projection (residual form, as in the iteration): lanes per
+        // ray, and taps from global memory or (where the stage fits) from LDS
+        std::vector<std::pair<int, int>> fps = {{def.fp_seg, def.fp_lds}};
+        for (int lds : {1, 2})
+            for (int v : {1, 2, 4, 8})
+                if ((lds == 1 || fp_lds_fits(p, k)) && std::make_pair(v, lds) != fps[0]) fps.push_back({v, lds});
+        std::pair<int, int> fpc = fps[0];
+        st = pick<std::pair<int, int>>(
+            fps,
+            [&](const std::pair<int, int>& c) {
+                p->cfg[k].fp_seg = c.first;
+                p->cfg[k].fp_lds = c.second;
                 return launch_fp(p, k, true, ViewSel{vp, n_sel}, b.f(), proj.f(), s);
             },
-            [&](std::vector<float>& h) { return download(h, proj.f(), nproj); }, s, &seg);
+            [&](std::vector<float>& h) { return download(h, proj.f(), nproj); }, s, &fpc);
         if (st != FB_OK) return st;
-        p->cfg[k].fp_seg = seg;
+        p->cfg[k].fp_seg = fpc.first;
+        p->cfg[k].fp_lds = fpc.second;
         // backprojection: the fused form is timed, the plain gradient compared
         std::vector<std::pair<int, int>> bps = {{def.bp_px, def.bp_vg}};
         for (auto c : bp_candidates(n_sel))
@@ -385,7 +393,7 @@ static fb_status autotune_batch(fb_batch* B, int n_sub, const char* cache_path, 
             (st = need(xp, (size_t)img_n, "x_prev")) != FB_OK || (st = need(xo, (size_t)img_n, "x_out")) != FB_OK ||
             (st = need(yo, (size_t)img_n, "y_out")) != FB_OK)
             return st;
-        B->cfg[k] = fb_launch_config{0, 0, 0, 0};
+        B->cfg[k] = fb_launch_config{0, 0, 0, 0, 0};
         const fb_launch_config def = batch_config(B, k, n_sub);
         if ((st = launch_prepare_batch(B, k, img.f(), s)) != FB_OK) return st;
         std::vector<int> segs = {def.fp_seg};
@@ -397,6 +405,7 @@ static fb_status autotune_batch(fb_batch* B, int n_sub, const char* cache_path, 
             [&](std::vector<float>& o) { return gather(true, o); }, s, &seg);
         if (st != FB_OK) return st;
         B->cfg[k].fp_seg = seg;
+        B->cfg[k].fp_lds = 1;
         int nsel_min = 1 << 30;
         for (const SliceDesc& D : B->h_desc) nsel_min = std::min(nsel_min, cdiv(D.n_views, n_sub));
         std::vector<std::pair<int, int>> bps = {{def.bp_px, def.bp_vg}};

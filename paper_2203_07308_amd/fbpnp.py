@@ -70,7 +70,7 @@ class PnpArgs(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("fp_seg", ctypes.c_int32), ("bp_px", ctypes.c_int32), ("bp_vg", ctypes.c_int32),
-                ("tv_tile", ctypes.c_int32)]
+                ("tv_tile", ctypes.c_int32), ("fp_lds", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

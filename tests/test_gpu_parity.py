@@ -112,22 +112,60 @@ def setup_case(name, f, sel):
     return gd, og, plan, views
 
 
+def fp_forms(plan, stage):
+    """Forward-projector launch shapes: the built-in one, and where the stage's line images
+    fit in LDS, the LDS-staged form with one and eight lanes per ray."""
+    forms = [None]
+    try:
+        plan.set_config(stage, dict(fp_seg=1, fp_lds=2))
+        forms += [dict(fp_seg=1, fp_lds=2), dict(fp_seg=8, fp_lds=2)]
+    except fbpnp.FbError:
+        pass
+    plan.set_config(stage, None)
+    return forms
+
+
 @pytest.mark.parametrize("name,f,sel", FP_CASES)
 def test_fanbeam_fp_matches_oracle(name, f, sel):
     gd, og, plan, views = setup_case(name, f, sel)
-    say("fp", name, f, sel)
     nys, nxs = gd["ny"] // f, gd["nx"] // f
     x = ellipse_image(nys, nxs, 11).astype(np.float32)
     n_sel = gd["n_views"] if views is None else len(views)
-    y = torch.empty(n_sel * gd["n_bins"], device="cuda")
-    fbpnp.fanbeam_fp(plan, 0, dev(x), y, None if views is None else dev(views, np.int32))
-    got = host(y).reshape(n_sel, gd["n_bins"])
     ref = oracle.fp(og, x.astype(np.float64), f, views)
-    for i in range(n_sel):
-        if np.linalg.norm(ref[i]) > 0:
-            assert rel(got[i], ref[i]) <= 1e-5, (i, rel(got[i], ref[i]))
-        else:
-            assert np.all(got[i] == 0)
+    outs = []
+    for form in fp_forms(plan, 0):
+        say("fp", name, f, sel, form)
+        plan.set_config(0, form)
+        y = torch.empty(n_sel * gd["n_bins"], device="cuda")
+        fbpnp.fanbeam_fp(plan, 0, dev(x), y, None if views is None else dev(views, np.int32))
+        got = host(y).reshape(n_sel, gd["n_bins"])
+        outs.append(got)
+        for i in range(n_sel):
+            if np.linalg.norm(ref[i]) > 0:
+                assert rel(got[i], ref[i]) <= 1e-5, (form, i, rel(got[i], ref[i]))
+            else:
+                assert np.all(got[i] == 0)
+    # the taps are the same floats wherever they are read from: the LDS form with the
+    # built-in lanes per ray equals the global one bit for bit
+    if len(outs) > 1:
+        plan.set_config(0, None)
+        seg = plan.get_config(0, n_sel)["fp_seg"]
+        plan.set_config(0, dict(fp_seg=seg, fp_lds=2))
+        y = torch.empty(n_sel * gd["n_bins"], device="cuda")
+        fbpnp.fanbeam_fp(plan, 0, dev(x), y, None if views is None else dev(views, np.int32))
+        np.testing.assert_array_equal(host(y).reshape(n_sel, gd["n_bins"]), outs[0])
+        plan.set_config(0, None)
+
+
+def test_fp_lds_refused_where_the_stage_does_not_fit():
+    gd = make_geom(**GEOMS["512"])
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [1, 4])
+    with pytest.raises(fbpnp.FbError):
+        plan.set_config(0, dict(fp_lds=2))
+    plan.set_config(1, dict(fp_lds=2))
+    assert plan.get_config(1)["fp_lds"] == 2
+    with pytest.raises(fbpnp.FbError):
+        plan.set_config(1, dict(fp_lds=3))
 
 
 # backprojector launch shapes: the built-in choice, each pixel block size of the gather form
@@ -515,10 +553,11 @@ def test_loop_ms2g512_subsets_multistage(tmp_path):
 
 def test_loop_ms2g256_two_stage_scatter_backprojection():
     """The 256^2 two-stage loop with the scatter back-projector at both stages (block sides 16
-    and 32), direct and as a graph, against the oracle's loop."""
+    and 32) and the LDS-staged projector at the 128^2 stage, direct and as a graph, against the
+    oracle's loop."""
     w, gd, og, xt, b = problem("ms2g256")
     plan = fbpnp.Plan(fbpnp.Geometry(**gd), [2, 1])
-    plan.set_config(0, dict(fp_seg=0, bp_px=16, bp_vg=16, tv_tile=0))
+    plan.set_config(0, dict(fp_seg=0, bp_px=16, bp_vg=16, tv_tile=0, fp_lds=2))
     plan.set_config(1, dict(fp_seg=0, bp_px=32, bp_vg=16, tv_tile=0))
     L2, L1 = oracle.power_lipschitz(og, 2, 60), oracle.power_lipschitz(og, 1, 60)
     eta = np.array([1 / L2] * 30 + [1 / L1] * 20)
