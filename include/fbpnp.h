@@ -368,7 +368,9 @@ fb_status fb_batch_autotune(fb_batch* batch, int n_sub, const char* cache_path, 
  * tv_prox_vjp: zbar = J^T xbar for the relaxed denoiser
  *   z -> (1 - alpha) z + alpha tv_prox(z; lambda, n_iter, tau),
  * recomputing the dual iterates; d|q|/dq is taken as 0 at q = 0. zbar must not
- * alias z or xbar. ws: at least fb_tv_vjp_workspace_bytes(nx, ny, n_iter).
+ * alias z or xbar. ws: at least fb_tv_vjp_workspace_bytes(nx, ny, n_iter) bytes;
+ * that is 0 for n_iter <= 5 (one launch recomputes every dual level on chip),
+ * and then ws may be NULL.
  */
 size_t fb_tv_vjp_workspace_bytes(int nx, int ny, int n_iter);
 fb_status tv_prox_vjp(const float* z, const float* xbar, float* zbar, int nx, int ny, float lambda, int n_iter,

@@ -174,8 +174,201 @@ __global__ __launch_bounds__(256) void k_axpy(const float* __restrict__ x, float
         y[i] = fmaf(a, x[i], y[i]);
 }
 
+// ---------------------------------------------------------------------------
+// TV-prox reverse sweep in one launch: each work-group recomputes the K dual
+// steps on a 32 x 32 output tile grown by a 12-cell halo (the recomputation
+// and the sweep back each move the influence of the tile's unknown
+// surroundings one cell per step, 2K + 1 <= 11 cells in all), keeping every
+// level p^1..p^K and u^0..u^{K-1} of its cells in registers and exchanging
+// neighbour values through LDS, then sweeps back through the levels and
+// writes zbar for the tile. Each cell's operations and their order are
+// those of the launch chain above (k_tvf_u, k_tvf_p, k_tvb_init, k_tvb_q,
+// k_tvb_up), so both give the same floats; the image-boundary conditions are
+// taken on global coordinates, and cells outside the image (halo) never feed
+// cells inside it. A thread owns vertical pairs of cells, as in the
+// denoiser.
+// ---------------------------------------------------------------------------
+constexpr int kVjpTile = 32, kVjpHalo = 12, kVjpMaxFused = 5;
+
+template <int K>
+__global__ __launch_bounds__(1024) void k_tv_vjp_tile(const float* __restrict__ z, const float* __restrict__ xbar,
+                                                      float* __restrict__ zbar, int nx, int ny, float il,
+                                                      float lam_alpha, float tau) {
+    constexpr int T = kVjpTile, H = kVjpHalo, S = T + 2 * H, NT = 1024;
+    constexpr int NPAIR = (S / 2) * S, NP = (NPAIR + NT - 1) / NT;
+    __shared__ float sa[S * S], sb[S * S], sc[S * S], sd[S * S];
+    const int R0 = blockIdx.y * T - H, C0 = blockIdx.x * T - H;
+    int e[NP], eu[NP][2], el[NP][2], ed[NP][2], er[NP][2], gr[NP], gc[NP];
+    bool live[NP], in[NP][2];
+    float zz[NP][2], xb[NP][2];
+    float P1[K + 1][NP][2], P2[K + 1][NP][2], U[K][NP][2];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int q = threadIdx.x + k * NT;
+        live[k] = q < NPAIR;
+        const int qq = live[k] ? q : NPAIR - 1;
+        const int pr = qq / S, lc = qq - pr * S, lr = 2 * pr;
+        e[k] = lr * S + lc;
+        gr[k] = R0 + lr;
+        gc[k] = C0 + lc;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = lr + h, ei = e[k] + h * S;
+            // neighbours inside the tile (at its edge the cell itself: those cells are halo)
+            eu[k][h] = r > 0 ? ei - S : ei;
+            ed[k][h] = r < S - 1 ? ei + S : ei;
+            el[k][h] = lc > 0 ? ei - 1 : ei;
+            er[k][h] = lc < S - 1 ? ei + 1 : ei;
+            const int g = gr[k] + h;
+            in[k][h] = g >= 0 && g < ny && gc[k] >= 0 && gc[k] < nx;
+            const size_t gi = (size_t)(in[k][h] ? g : 0) * nx + (in[k][h] ? gc[k] : 0);
+            zz[k][h] = in[k][h] ? z[gi] : 0.f;
+            xb[k][h] = in[k][h] ? xbar[gi] : 0.f;
+            P1[0][k][h] = P2[0][k][h] = 0.f;
+            if (live[k]) sa[ei] = sb[ei] = 0.f;
+        }
+    }
+    __syncthreads();
+    // forward: u^n = div p^n - z / lambda, p^{n+1} = (p^n + tau q^n) / (1 + tau |q^n|)
+#pragma unroll
+    for (int n = 0; n < K; ++n) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float up = gr[k] + h > 0 ? sa[eu[k][h]] : 0.f;
+                const float left = gc[k] > 0 ? sb[el[k][h]] : 0.f;
+                U[n][k][h] = (P1[n][k][h] - up) + (P2[n][k][h] - left) - zz[k][h] * il;
+            }
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (live[k]) sc[e[k] + h * S] = U[n][k][h];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float q1 = gr[k] + h < ny - 1 ? sc[ed[k][h]] - U[n][k][h] : 0.f;
+                const float q2 = gc[k] < nx - 1 ? sc[er[k][h]] - U[n][k][h] : 0.f;
+                const float inv =
+                    __builtin_amdgcn_rcpf(fmaf(tau, __builtin_amdgcn_sqrtf(fmaf(q1, q1, q2 * q2)), 1.f));
+                P1[n + 1][k][h] = fmaf(tau, q1, P1[n][k][h]) * inv;
+                P2[n + 1][k][h] = fmaf(tau, q2, P2[n][k][h]) * inv;
+            }
+        if (n + 1 < K) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    if (live[k]) {
+                        sa[e[k] + h * S] = P1[n + 1][k][h];
+                        sb[e[k] + h * S] = P2[n + 1][k][h];
+                    }
+        }
+        __syncthreads();
+    }
+    // reverse: zbar = xbar, pbar^K = -lambda alpha div^T xbar
+    float zb[NP][2], pb1[NP][2], pb2[NP][2];
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (live[k]) {
+                sc[e[k] + h * S] = xb[k][h];
+                sd[e[k] + h * S] = U[K - 1][k][h];
+            }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            zb[k][h] = xb[k][h];
+            pb1[k][h] = gr[k] + h < ny - 1 ? -lam_alpha * (xb[k][h] - sc[ed[k][h]]) : 0.f;
+            pb2[k][h] = gc[k] < nx - 1 ? -lam_alpha * (xb[k][h] - sc[er[k][h]]) : 0.f;
+        }
+#pragma unroll
+    for (int n = K - 1; n >= 0; --n) {
+        // qbar from pbar^{n+1}, q^n (u^n of the cell and its neighbours) and p^{n+1}
+        float qb1[NP][2], qb2[NP][2];
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float q1 = gr[k] + h < ny - 1 ? sd[ed[k][h]] - U[n][k][h] : 0.f;
+                const float q2 = gc[k] < nx - 1 ? sd[er[k][h]] - U[n][k][h] : 0.f;
+                const float mag = sqrtf(fmaf(q1, q1, q2 * q2));
+                const float den = fmaf(tau, mag, 1.f);
+                const float b1 = pb1[k][h], b2 = pb2[k][h];
+                const float nb1 = b1 / den, nb2 = b2 / den;
+                const float db = -fmaf(b1, P1[n + 1][k][h], b2 * P2[n + 1][k][h]) / den;
+                const float mb = mag > 0.f ? tau * db / mag : 0.f;
+                qb1[k][h] = fmaf(tau, nb1, mb * q1);
+                qb2[k][h] = fmaf(tau, nb2, mb * q2);
+                pb1[k][h] = nb1;
+                pb2[k][h] = nb2;
+            }
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (live[k]) {
+                    sa[e[k] + h * S] = qb1[k][h];
+                    sb[e[k] + h * S] = qb2[k][h];
+                }
+        __syncthreads();
+        // ubar = (masked grad)^T qbar at the cell
+        float ub[NP][2];
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int rr = gr[k] + h, cc = gc[k];
+                float s = 0.f;
+                if (rr < ny - 1) s -= qb1[k][h];
+                if (rr > 0) s += sa[eu[k][h]];
+                if (cc < nx - 1) s -= qb2[k][h];
+                if (cc > 0) s += sb[el[k][h]];
+                ub[k][h] = s;
+            }
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (live[k]) sc[e[k] + h * S] = ub[k][h];
+        __syncthreads();
+        // pbar^n = Nbar + div^T ubar, zbar -= ubar / lambda; and u^{n-1} for the next step
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float u0 = ub[k][h];
+                if (gr[k] + h < ny - 1) pb1[k][h] += u0 - sc[ed[k][h]];
+                if (gc[k] < nx - 1) pb2[k][h] += u0 - sc[er[k][h]];
+                zb[k][h] -= u0 * il;
+                if (n > 0 && live[k]) sd[e[k] + h * S] = U[n - 1][k][h];
+            }
+        __syncthreads();
+    }
+    // the output tile
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int pr = (live[k] ? threadIdx.x + k * NT : NPAIR - 1) / S;
+        const int lc = e[k] - 2 * pr * S;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int lr = 2 * pr + h;
+            if (live[k] && in[k][h] && lr >= H && lr < H + T && lc >= H && lc < H + T)
+                zbar[(size_t)(gr[k] + h) * nx + gc[k]] = zb[k][h];
+        }
+    }
+}
+
 size_t tv_ws_floats(int nx, int ny, int n_iter) {
-    // p levels 0..K (two planes each), u levels 0..K-1, pbar, qbar
+    // up to kVjpMaxFused steps the one-launch sweep keeps every level on chip;
+    // beyond, p levels 0..K (two planes each), u levels 0..K-1, pbar, qbar
+    if (n_iter <= kVjpMaxFused) return 0;
     return (size_t)nx * ny * (size_t)(2 * (n_iter + 1) + n_iter + 4);
 }
 
@@ -187,6 +380,18 @@ fb_status launch_tv_vjp(const float* z, const float* xbar, float* zbar, int nx, 
     if (lam == 0.f || K == 0 || alpha == 0.f) {
         hipError_t e = hipMemcpyAsync(zbar, xbar, n * sizeof(float), hipMemcpyDeviceToDevice, s);
         return e == hipSuccess ? FB_OK : hip_fail(e, "tv vjp copy");
+    }
+    if (K <= kVjpMaxFused) {
+        const dim3 tiles(cdiv(nx, kVjpTile), cdiv(ny, kVjpTile));
+        const float il = 1.f / lam, la = lam * alpha;
+        switch (K) {
+            case 1: k_tv_vjp_tile<1><<<tiles, 1024, 0, s>>>(z, xbar, zbar, nx, ny, il, la, tau); break;
+            case 2: k_tv_vjp_tile<2><<<tiles, 1024, 0, s>>>(z, xbar, zbar, nx, ny, il, la, tau); break;
+            case 3: k_tv_vjp_tile<3><<<tiles, 1024, 0, s>>>(z, xbar, zbar, nx, ny, il, la, tau); break;
+            case 4: k_tv_vjp_tile<4><<<tiles, 1024, 0, s>>>(z, xbar, zbar, nx, ny, il, la, tau); break;
+            default: k_tv_vjp_tile<5><<<tiles, 1024, 0, s>>>(z, xbar, zbar, nx, ny, il, la, tau); break;
+        }
+        return check_launch("tv_prox_vjp");
     }
     float* P = ws;                       // level k: P + 2 k n (p1), + n (p2)
     float* U = P + 2 * (size_t)(K + 1) * n;  // level k: U + k n
@@ -224,8 +429,8 @@ fb_status tv_prox_vjp(const float* z, const float* xbar, float* zbar, int nx, in
     if (!z || !xbar || !zbar || nx < 1 || ny < 1 || n_iter < 0) return fail(FB_EINVAL, "tv_prox_vjp: bad arguments");
     if (!(lambda >= 0.f) || !(tau > 0.f)) return fail(FB_EINVAL, "tv_prox_vjp: need lambda >= 0 and tau > 0");
     if (zbar == xbar || zbar == z) return fail(FB_EINVAL, "tv_prox_vjp: zbar must not alias the inputs");
-    if (!ws || ws_bytes < fb_tv_vjp_workspace_bytes(nx, ny, n_iter))
-        return fail(FB_EINVAL, "tv_prox_vjp: workspace too small");
+    const size_t need = fb_tv_vjp_workspace_bytes(nx, ny, n_iter);
+    if (need > 0 && (!ws || ws_bytes < need)) return fail(FB_EINVAL, "tv_prox_vjp: workspace too small");
     return launch_tv_vjp(z, xbar, zbar, nx, ny, lambda, n_iter, tau, alpha, (float*)ws, stream);
 }
 

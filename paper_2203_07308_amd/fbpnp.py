@@ -545,11 +545,12 @@ def tv_prox_vjp(z: torch.Tensor, xbar: torch.Tensor, zbar: torch.Tensor, lam: fl
     """zbar = J^T xbar of z -> (1 - alpha) z + alpha tv_prox(z)."""
     ny, nx = z.shape
     need = int(load().fb_tv_vjp_workspace_bytes(nx, ny, n_iter))
-    if ws is None:
+    if ws is None and need > 0:
         ws = torch.empty((need + 3) // 4, dtype=torch.float32, device=z.device)
+    ws_ptr, ws_bytes = (ws.data_ptr(), ws.numel() * 4) if ws is not None else (None, 0)
     _check(load().tv_prox_vjp(_ptr(z, name="z"), _ptr(xbar, numel=nx * ny, name="xbar"),
                               _ptr(zbar, numel=nx * ny, name="zbar"), nx, ny, float(lam), int(n_iter), float(tau),
-                              float(alpha), ctypes.c_void_p(ws.data_ptr()), ws.numel() * 4, _stream(stream)))
+                              float(alpha), ctypes.c_void_p(ws_ptr), ws_bytes, _stream(stream)))
     return zbar
 
 

@@ -88,6 +88,16 @@ def test_tv_workspace_size():
     assert lib.fb_tv_workspace_bytes(64, 32, 9) == 4 * 64 * 32 * 4
 
 
+def test_tv_vjp_workspace_size():
+    """Up to 5 denoiser steps the reverse sweep runs in one launch with no workspace."""
+    lib = fbpnp.load()
+    for k in range(6):
+        assert lib.fb_tv_vjp_workspace_bytes(64, 32, k) == 0
+    # p levels 0..K (two planes each), u levels 0..K-1, pbar and qbar (two planes each)
+    assert lib.fb_tv_vjp_workspace_bytes(64, 32, 6) == 4 * 64 * 32 * (2 * 7 + 6 + 4)
+    assert lib.fb_tv_vjp_workspace_bytes(0, 32, 6) == 0
+
+
 def test_struct_layouts_match_header(tmp_path):
     """ctypes mirrors agree with the C compiler's layout of the header's structs."""
     import shutil
