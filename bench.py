@@ -139,6 +139,9 @@ def parse():
     ap.add_argument("--forms-summary", nargs=2, metavar=("TRACE_DIR", "LOG"),
                     help="kernel durations per form from a rocprofv3 kernel trace of --forms and its log (no GPU use)")
     ap.add_argument("--bench-log", help="log of the profiled command (its JSON line is quoted in a trace summary)")
+    ap.add_argument("--section", choices=("differentiation", "batched", "scenarios"),
+                    help="run only that workload (as the full run does, with its own set-up) and log its result; "
+                         "for kernel traces of one workload (no JSON line)")
     return ap.parse_args()
 
 
@@ -464,6 +467,15 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.forms:
         return projector_forms(torch, fbpnp, synth)
+    if args.section == "differentiation":
+        differentiation_section(torch, fbpnp, synth, tune_cache_path(args), reps=max(args.steps, 1))
+        return 0
+    if args.section == "batched":
+        batched_section(torch, fbpnp, synth, args.batch_steps, tune_cache_path(args))
+        return 0
+    if args.section == "scenarios":
+        paper_scenarios(torch, fbpnp, synth, tune_cache_path(args))
+        return 0
     w = synth.WORKLOADS["ms2g512"]
     gd = w.geometry
     V, B, N = gd["n_views"], gd["n_bins"], gd["nx"]
@@ -527,6 +539,7 @@ def main() -> int:
         for n_sel in (V, V // n_sub):
             plan.autotune(n_sel=n_sel, cache_path=tune_cache)
         batched_section(torch, fbpnp, synth, 0, tune_cache, tune_only=True)
+        differentiation_section(torch, fbpnp, synth, tune_cache, tune_only=True)
         log(f"autotuner cache written to {tune_cache}")
         return 0
     plan.autotune(n_sel=V // n_sub, cache_path=tune_cache)
@@ -659,7 +672,7 @@ def main() -> int:
     # ---- the differentiation workload: reverse mode through unrolled iterations
     diff = None
     if not args.no_diff:
-        diff = differentiation_section(torch, fbpnp, synth)
+        diff = differentiation_section(torch, fbpnp, synth, tune_cache)
 
     # ---- the paper's own experiment shapes: two-stage sketch against PnP-FISTA
     scen = None
@@ -706,7 +719,7 @@ def main() -> int:
     return 0
 
 
-def differentiation_section(torch, fbpnp, synth, reps=3):
+def differentiation_section(torch, fbpnp, synth, tune_cache, reps=3, tune_only=False):
     """Reverse mode through 10 unrolled two-stage sketched iterations (5 at f = 2, then 5 at
     f = 1, FISTA momentum, all views) on a batch of 8 slices of 512^2 with 360 views x 768
     bins (seeded 20-ellipse phantoms, 1% Gaussian noise): the GPU time of the forward pass
@@ -718,6 +731,11 @@ def differentiation_section(torch, fbpnp, synth, reps=3):
     n, V, nb, S, n2, n1 = 512, 360, 768, 8, 5, 5
     gd = synth.fan_geometry(n, V, nb)
     plan = fbpnp.Plan(fbpnp.Geometry(**gd), [2, 1])
+    # every iteration takes all views: launch configurations tuned for that view count
+    plan.autotune(n_sel=V, cache_path=tune_cache)
+    if tune_only:
+        plan.close()
+        return None
     xts = np.stack([synth.rasterise(synth.random_ellipses(6000 + s, 20, n), n) for s in range(S)]).astype(np.float32)
     xt_d = torch.from_numpy(xts).cuda()
     ax = torch.empty((S, V * nb), device="cuda")
