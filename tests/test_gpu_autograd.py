@@ -98,17 +98,21 @@ def schedule(gd, n_f2, n_f1, subsets, fc=2):
     return sched_o, specs, a
 
 
-def run_case(gd, og, xt, b, n_f2, n_f1, subsets, x0, eta, fc=2):
+def run_case(gd, og, xt, b, n_f2, n_f1, subsets, x0, eta, fc=2, tv_iters=5, alpha=1.0):
     plan = fbpnp.Plan(fbpnp.Geometry(**gd), [fc, 1])
     sched_o, specs, a = schedule(gd, n_f2, n_f1, subsets, fc)
+    for st in specs:
+        st.tv_iters, st.alpha = tv_iters, alpha
     x0_t = dev(x0).requires_grad_(True)
     eta_t = torch.tensor(eta, dtype=torch.float32, device="cuda", requires_grad=True)
     xT = unrolled_pnp(plan, dev(b).reshape(-1), specs, x0_t, eta_t)
     loss = 0.5 * ((xT - dev(xt)) ** 2).sum()
     loss.backward()
     g_x0, g_eta = host(x0_t.grad), host(eta_t.grad)
+    kw = dict(tv_iters=tv_iters, alpha=alpha)
     r_x0, r_eta = oracle.pnp_vjp(og, b.astype(np.float64), sched_o, eta, a,
-                                 oracle.pnp_run(og, b.astype(np.float64), sched_o, eta, a, x0=x0) - xt, x0=x0)
+                                 oracle.pnp_run(og, b.astype(np.float64), sched_o, eta, a, x0=x0, **kw) - xt, x0=x0,
+                                 **kw)
     return g_x0, g_eta, r_x0, r_eta, sched_o, a
 
 
@@ -134,6 +138,21 @@ def test_unrolled_gradients_match_oracle_small():
         e[t] = h * eta[t]
         fd = (loss(x0, eta + e) - loss(x0, eta - e)) / (2 * e[t])
         assert abs(fd - g_eta[t]) <= 1e-3 * max(abs(fd), 1e-6 * np.abs(r_eta).max()), (t, fd, g_eta[t])
+
+
+@pytest.mark.parametrize("tv_iters,alpha", [(7, 1.0), (3, 0.7)])
+def test_unrolled_gradients_other_denoiser_step_counts(tv_iters, alpha):
+    """6 unrolled iterations at 48^2 (3 at f = 2, 3 at f = 1, 1 of 3 view subsets) with 7 denoiser
+    steps, whose reverse sweep is the launch chain with its workspace inside the step's own
+    workspace, and with 3 steps and relaxation alpha < 1 (the one-launch sweep)."""
+    gd, og, xts, bs = make_problem(48, 60, 72, 17)
+    L = oracle.power_lipschitz(og, 1, 50)
+    eta = np.full(6, 1.0 / L)
+    x0 = (0.5 * xts[0]).astype(np.float32).astype(np.float64)
+    say(f"unrolled 48, tv_iters {tv_iters}, alpha {alpha}")
+    g_x0, g_eta, r_x0, r_eta, *_ = run_case(gd, og, xts[0], bs[0], 3, 3, 3, x0, eta, tv_iters=tv_iters, alpha=alpha)
+    assert rel(g_x0, r_x0) <= 1e-3, rel(g_x0, r_x0)
+    assert rel(g_eta, r_eta) <= 1e-3, (g_eta, r_eta)
 
 
 def test_unrolled_gradients_coarse_factor_three():
