@@ -250,8 +250,13 @@ fb_status tv_prox_noalloc(const float* z, float* x, int nx, int ny, float lambda
  *      g_M(y) - g_M(y_snap) + g(y_snap) with the last snapshot of this stage.
  * A snapshot's buffers belong to one stage; take a new snapshot when the stage
  * changes.
+ * grad (optional, vr_mode 0 only): device [nys][nxs] of the stage. pnp_step
+ * stores the unscaled coarse gradient (M A_s)^T (M A_s v - M b) there, so G =
+ * sigma grad; pnp_step_vjp reads it back instead of recomputing it (a
+ * checkpoint for reverse mode; it must come from the forward step at the same
+ * inputs).
  * Every optional field (history, events, vr_mode and its buffers, n_sub,
- * subset) means "not used" at zero: zero-initialise the struct
+ * subset, grad) means "not used" at zero: zero-initialise the struct
  * (fb_pnp_args a = {0}) and set the fields in use.
  */
 typedef struct fb_pnp_args {
@@ -274,6 +279,7 @@ typedef struct fb_pnp_args {
     float* snap_proj;
     float* snap_grad;
     int32_t n_sub, subset;
+    float* grad;
 } fb_pnp_args;
 fb_status pnp_step(const fb_plan* plan, const fb_pnp_args* args, hipStream_t stream);
 
@@ -379,7 +385,9 @@ fb_status tv_prox_vjp(const float* z, const float* xbar, float* zbar, int nx, in
 /*
  * pnp_step_vjp: reverse mode of one pnp_step (Sec. 2.1, Algorithm 1) at the
  * inputs in args (b, y_prev, views, sigma, eta, alpha, a_t, lambda, tau,
- * tv_iters; x_out, y_out and history are ignored; vr_mode must be 0). Given the adjoints
+ * tv_iters, and grad: the coarse gradient the forward step stored, or NULL to
+ * recompute it; x_out, y_out and history are ignored; vr_mode must be 0).
+ * Given the adjoints
  * xbar = dL/dx_t and ybar = dL/dy_t (ybar may be NULL for 0), computes
  *   xbar_prev = dL/dx_{t-1} = -a_t ybar            (may be NULL)
  *   ybar_prev = dL/dy_{t-1} = zbar - eta H zbar,    zbar = J_relax^T (xbar + (1 + a_t) ybar)

@@ -4,8 +4,9 @@
 walks them in reverse with ``pnp_step_vjp``: the matched projector pair is its own
 adjoint, the TV-prox is differentiated through its dual iterations, and each
 iteration's internals are recomputed from a per-iteration checkpoint of its inputs
-(x_{t-1}, y_{t-1}). Gradients are returned for the initial image x_0 (= y_0) and for
-every step size eta_t. Batches of slices share the step sizes; their eta gradients
+(x_{t-1}, y_{t-1}) and of its coarse gradient, which the forward step stores (so the
+reverse step needs no forward projection of its own). Gradients are returned for the
+initial image x_0 (= y_0) and for every step size eta_t. Batches of slices share the step sizes; their eta gradients
 add up. All arithmetic runs in the library's kernels; this module only orders the
 calls and keeps the checkpoints.
 """
@@ -43,25 +44,29 @@ class UnrolledPnP(torch.autograd.Function):
         assert eta.numel() == T
         etas = [float(v) for v in eta.detach().cpu().tolist()]
         npix = plan.geom.nx * plan.geom.ny
-        ckpt_x, ckpt_y, outs = [], [], []
+        ckpt_x, ckpt_y, ckpt_g, outs = [], [], [], []
         for s in range(x0b.shape[0]):
             x = x0b[s].reshape(-1).contiguous().clone()
             y = x.clone()
-            xs, ys = [], []
+            xs, ys, gs = [], [], []
             for t, st in enumerate(steps):
                 xs.append(x)
                 ys.append(y)
+                nys, nxs = plan.coarse_shape(st.stage)
+                g = torch.empty(nys * nxs, device=x.device)
+                gs.append(g)
                 xn = torch.empty(npix, device=x.device)
                 yn = torch.empty(npix, device=x.device)
                 args = fbpnp.pnp_args(plan, st.stage, bb[s].contiguous(), y, x, xn, yn, etas[t], st.a_t, st.views,
-                                      st.sigma, st.alpha, st.lam, st.tau, st.tv_iters)
+                                      st.sigma, st.alpha, st.lam, st.tau, st.tv_iters, grad=g)
                 fbpnp.pnp_step(plan, args)
                 x, y = xn, yn
             ckpt_x.append(xs)
             ckpt_y.append(ys)
+            ckpt_g.append(gs)
             outs.append(x.reshape(plan.geom.ny, plan.geom.nx))
         ctx.plan, ctx.steps, ctx.etas, ctx.single = plan, steps, etas, single
-        ctx.ckpt_x, ctx.ckpt_y = ckpt_x, ckpt_y
+        ctx.ckpt_x, ctx.ckpt_y, ctx.ckpt_g = ckpt_x, ckpt_y, ckpt_g
         ctx.b = bb
         out = torch.stack(outs)
         return out[0] if single else out
@@ -83,7 +88,8 @@ class UnrolledPnP(torch.autograd.Function):
                 st = steps[t]
                 y_prev, x_prev = ctx.ckpt_y[s][t], ctx.ckpt_x[s][t]
                 args = fbpnp.pnp_args(plan, st.stage, ctx.b[s].contiguous(), y_prev, x_prev, x_prev, y_prev,
-                                      etas[t], st.a_t, st.views, st.sigma, st.alpha, st.lam, st.tau, st.tv_iters)
+                                      etas[t], st.a_t, st.views, st.sigma, st.alpha, st.lam, st.tau, st.tv_iters,
+                                      grad=ctx.ckpt_g[s][t])
                 combine = t == 0
                 xbar_prev = None if combine else torch.empty(npix, device=gx.device)
                 ybar_prev = torch.empty(npix, device=gx.device)

@@ -841,8 +841,12 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
     // a snapshot fills every row of snap_proj: all views, in order, each once
     if (a->vr_mode == 1 && (a->views || a->n_sub > 1 || a->n_sel != p->g.n_views))
         return fail(FB_EINVAL, "pnp_step: a snapshot step takes every view (views NULL, no subset)");
+    if (a->grad && a->vr_mode != 0) return fail(FB_EINVAL, "pnp_step: grad is for minibatch steps (vr_mode 0)");
     const Stage& S = p->stages[a->stage];
-    if (bicubic_stage(p, a->stage)) return pnp_step_bicubic(p, a, stream);
+    if (bicubic_stage(p, a->stage)) {
+        if (a->grad) return fail(FB_EINVAL, "pnp_step: grad is stored with the pooling sketch only");
+        return pnp_step_bicubic(p, a, stream);
+    }
     if (!a->prepared && (st = launch_prepare(p, a->stage, a->y_prev, p->g.nx, S.f, stream)) != FB_OK) return st;
     // variance-reduced modes: 1 records the snapshot's projection and coarse
     // gradient; 2 projects against the snapshot's projection and adds its gradient
@@ -858,7 +862,7 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
         TimedLaunch tl(a->events, 2);
         if ((st = launch_bp_t<true>(p, a->stage, p->resid, pnp_views(a), step, nullptr, a->y_prev, p->zbuf,
                                     stream, vr ? a->snap_grad : nullptr, a->eta / (float)(S.f * S.f),
-                                    snap ? a->snap_grad : nullptr)) != FB_OK)
+                                    snap ? a->snap_grad : a->grad)) != FB_OK)
             return st;
     }
     return step_tv(p, a, stream);

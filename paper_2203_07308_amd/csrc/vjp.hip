@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_tvb_up(const float* __restrict__ qb1, c
 // ---------------------------------------------------------------------------
 
 // z = y_prev - (eta / f^2) gs[r/f][c/f];  xtot = xbar + (1 + a) ybar;  xbar_prev = -a ybar
-__global__ __launch_bounds__(256) void k_vjp_front(const float* __restrict__ yprev, const float* __restrict__ gs,
+__global__ __launch_bounds__(256) void k_vjp_front(const float* __restrict__ yprev, const float* __restrict__ g,
                                                    int f, int nxs, float step, const float* __restrict__ xbar,
                                                    const float* __restrict__ ybar, float a_t, int nx,
                                                    float* __restrict__ z, float* __restrict__ xtot,
@@ -126,7 +126,8 @@ __global__ __launch_bounds__(256) void k_vjp_front(const float* __restrict__ ypr
     const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
     if (c >= nx) return;
     const size_t i = (size_t)r * nx + c;
-    z[i] = yprev[i] - step * gs[(size_t)(r / f) * nxs + c / f];
+    // the forward step's z, with its rounding (the fused back-projector's epilogue)
+    z[i] = fmaf(-step, g[(size_t)(r / f) * nxs + c / f], yprev[i]);
     const float yb = ybar ? ybar[i] : 0.f;
     xtot[i] = fmaf(1.f + a_t, yb, xbar[i]);
     if (xbar_prev) xbar_prev[i] = -a_t * yb;
@@ -463,7 +464,7 @@ fb_status pnp_step_vjp(const fb_plan* p, const fb_pnp_args* a, const float* xbar
         return fail(FB_EINVAL, "pnp_step_vjp: workspace too small");
     if ((uintptr_t)ws % 256 != 0) return fail(FB_EINVAL, "pnp_step_vjp: workspace must be 256-byte aligned");
     const float* outs[] = {xbar_prev, ybar_prev};
-    const float* ins[] = {xbar, ybar, a->y_prev, a->x_prev, a->b};
+    const float* ins[] = {xbar, ybar, a->y_prev, a->x_prev, a->b, a->grad};
     for (const float* o : outs)
         for (const float* q : ins)
             if (o && o == q) return fail(FB_EINVAL, "pnp_step_vjp: outputs must not alias inputs");
@@ -478,22 +479,29 @@ fb_status pnp_step_vjp(const fb_plan* p, const fb_pnp_args* a, const float* xbar
     float* tvws = gs + n;
     double* part = (double*)((float*)ws + vjp_part_offset_floats(nx, ny, a->tv_iters));
     const dim3 grid(cdiv(nx, 256), ny);
-    // forward recomputation: gs = sigma A_s^T M (M A_s S y - M b), z = y - eta U gs
-    if ((st = launch_prepare(p, a->stage, a->y_prev, nx, f, stream)) != FB_OK) return st;
-    if ((st = launch_fp(p, a->stage, true, pnp_views(a), a->b, p->resid, stream)) != FB_OK) return st;
-    if ((st = launch_bp(p, a->stage, p->resid, pnp_views(a), a->sigma, gs, nullptr, nullptr, false, stream)) !=
-        FB_OK)
-        return st;
+    // the unscaled coarse gradient g = A_s^T M (M A_s S y - M b) of the step
+    // (G = sigma g): stored by the forward step, or recomputed with the same
+    // kernels and launch configuration, so it has the same bits either way
+    const float* g = a->grad;
+    if (!g) {
+        if ((st = launch_prepare(p, a->stage, a->y_prev, nx, f, stream)) != FB_OK) return st;
+        if ((st = launch_fp(p, a->stage, true, pnp_views(a), a->b, p->resid, stream)) != FB_OK) return st;
+        if ((st = launch_bp(p, a->stage, p->resid, pnp_views(a), 1.f, gs, nullptr, nullptr, false, stream)) != FB_OK)
+            return st;
+        g = gs;
+    }
+    // z = y - eta sigma U g, as the forward step rounds it
     const float inv_ff = 1.f / (float)(f * f);
-    k_vjp_front<<<grid, 256, 0, stream>>>(a->y_prev, gs, f, S.nxs, a->eta * inv_ff, xbar, ybar, a->a_t, nx, z, xtot,
+    const float step = a->eta * a->sigma / (float)(f * f);
+    k_vjp_front<<<grid, 256, 0, stream>>>(a->y_prev, g, f, S.nxs, step, xbar, ybar, a->a_t, nx, z, xtot,
                                           combine ? nullptr : xbar_prev);
     if ((st = check_launch("pnp_step_vjp front")) != FB_OK) return st;
     // zbar = J_relax^T xtot
     const int K = a->lambda > 0.f ? a->tv_iters : 0;
     if ((st = launch_tv_vjp(z, xtot, zbar, nx, ny, a->lambda, K, a->tau, a->alpha, tvws, stream)) != FB_OK) return st;
-    // eta_bar = -<zbar, U gs>
-    k_dot_rep<<<kRedBlocks, 256, 0, stream>>>(zbar, gs, f, S.nxs, nx, n, part);
-    k_dot_final<<<1, 256, 0, stream>>>(part, kRedBlocks, -(double)inv_ff, eta_bar);
+    // eta_bar = -<zbar, U G> = -(sigma / f^2) <zbar, g replicated>
+    k_dot_rep<<<kRedBlocks, 256, 0, stream>>>(zbar, g, f, S.nxs, nx, n, part);
+    k_dot_final<<<1, 256, 0, stream>>>(part, kRedBlocks, -(double)a->sigma / (double)(f * f), eta_bar);
     if ((st = check_launch("pnp_step_vjp eta")) != FB_OK) return st;
     // ybar_prev = zbar - eta sigma U A_s^T M^T M A_s S zbar
     if ((st = launch_prepare(p, a->stage, zbar, nx, f, stream)) != FB_OK) return st;

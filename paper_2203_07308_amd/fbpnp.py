@@ -64,7 +64,7 @@ class PnpArgs(ctypes.Structure):
         ("next_stage", ctypes.c_int32), ("prepared", ctypes.c_int32),
         ("events", ctypes.POINTER(ctypes.c_void_p)),
         ("vr_mode", ctypes.c_int32), ("snap_proj", ctypes.c_void_p), ("snap_grad", ctypes.c_void_p),
-        ("n_sub", ctypes.c_int32), ("subset", ctypes.c_int32),
+        ("n_sub", ctypes.c_int32), ("subset", ctypes.c_int32), ("grad", ctypes.c_void_p),
     ]
 
 
@@ -348,13 +348,16 @@ def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float
              views: torch.Tensor | None = None, sigma: float = 1.0, alpha: float = 1.0, lam: float = 0.01,
              tau: float = 0.125, tv_iters: int = 5, history: torch.Tensor | None = None,
              events=None, vr_mode: int = 0, snap_proj: torch.Tensor | None = None,
-             snap_grad: torch.Tensor | None = None, subset: tuple[int, int] | None = None) -> PnpArgs:
+             snap_grad: torch.Tensor | None = None, subset: tuple[int, int] | None = None,
+             grad: torch.Tensor | None = None) -> PnpArgs:
     """Arguments of one pnp_step. events: optional sequence of six torch.cuda.Event
     (enable_timing=True) or None, recorded around the step's fp, bp and TV kernels.
     vr_mode 1 / 2 with snap_proj [n_views * n_bins] and snap_grad (the stage's coarse
     image size): variance-reduced snapshot / step (see include/fbpnp.h).
     subset = (k, n_sub), with views None: the interleaved subset k, k + n_sub, ...
-    of the views, whose indices the kernels compute instead of reading a list."""
+    of the views, whose indices the kernels compute instead of reading a list.
+    grad (the stage's coarse image size): pnp_step stores the coarse gradient there,
+    and pnp_step_vjp reads it back instead of recomputing it."""
     npix = plan.geom.nx * plan.geom.ny
     if subset is not None and views is not None:
         raise ValueError("pnp_args: give views or subset, not both")
@@ -373,6 +376,9 @@ def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float
         a.vr_mode = vr_mode
         a.snap_proj = _ptr(snap_proj, numel=plan.geom.n_views * plan.geom.n_bins, name="snap_proj")
         a.snap_grad = _ptr(snap_grad, numel=nxs * nys, name="snap_grad")
+    if grad is not None:
+        nys, nxs = plan.coarse_shape(stage)
+        a.grad = _ptr(grad, numel=nxs * nys, name="grad")
     if events is not None:
         if len(events) != 6:
             raise ValueError("events: need six entries (fp, bp, TV; begin and end)")

@@ -114,7 +114,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fb_geom), offsetof(fb_geom, angle_step_rad),
          sizeof(fb_stage_info), sizeof(fb_pnp_args), offsetof(fb_pnp_args, b),
          offsetof(fb_pnp_args, tv_iters), offsetof(fb_pnp_args, history), offsetof(fb_pnp_args, events));
-  printf("%zu %zu\\n", offsetof(fb_pnp_args, vr_mode), offsetof(fb_pnp_args, snap_grad));
+  printf("%zu %zu %zu\\n", offsetof(fb_pnp_args, vr_mode), offsetof(fb_pnp_args, snap_grad),
+         offsetof(fb_pnp_args, grad));
   printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(fb_launch_config), sizeof(fb_batch_args), offsetof(fb_batch_args, eta),
          offsetof(fb_batch_args, tv_iters), offsetof(fb_batch_args, history), offsetof(fb_batch_args, events));
   return 0;
@@ -127,7 +128,7 @@ int main(void) {
     want = [ctypes.sizeof(fbpnp.Geom), fbpnp.Geom.angle_step_rad.offset, ctypes.sizeof(fbpnp.StageInfo),
             ctypes.sizeof(fbpnp.PnpArgs), fbpnp.PnpArgs.b.offset, fbpnp.PnpArgs.tv_iters.offset,
             fbpnp.PnpArgs.history.offset, fbpnp.PnpArgs.events.offset,
-            fbpnp.PnpArgs.vr_mode.offset, fbpnp.PnpArgs.snap_grad.offset,
+            fbpnp.PnpArgs.vr_mode.offset, fbpnp.PnpArgs.snap_grad.offset, fbpnp.PnpArgs.grad.offset,
             ctypes.sizeof(fbpnp.LaunchConfig), ctypes.sizeof(fbpnp.BatchArgs), fbpnp.BatchArgs.eta.offset,
             fbpnp.BatchArgs.tv_iters.offset, fbpnp.BatchArgs.history.offset, fbpnp.BatchArgs.events.offset]
     assert got == want

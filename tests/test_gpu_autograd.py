@@ -155,6 +155,60 @@ def test_unrolled_gradients_other_denoiser_step_counts(tv_iters, alpha):
     assert rel(g_eta, r_eta) <= 1e-3, (g_eta, r_eta)
 
 
+@pytest.mark.parametrize("fc,subsets", [(2, 3), (1, 0), (3, 5)])
+def test_step_vjp_with_stored_gradient_equals_recomputation(fc, subsets):
+    """pnp_step stores the coarse gradient g (G = sigma U g) when grad is set; it matches the oracle's
+    gradient, and pnp_step_vjp fed with it gives bitwise the results of the reverse step that
+    recomputes g (same kernels and launch configuration)."""
+    n, V, nb = 60, 45, 90
+    gd, og, xts, bs = make_problem(n, V, nb, 23)
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [fc, 1])
+    rng = np.random.default_rng(29)
+    y_prev = (0.5 * xts[0] + 0.05 * rng.random((n, n))).astype(np.float32)
+    x_prev = (0.4 * xts[0]).astype(np.float32)
+    views = synth.subset_views(1, subsets, V) if subsets else None
+    sigma = float(subsets) if subsets else 1.0
+    eta = 1.0 / oracle.power_lipschitz(og, fc, 50)
+    nys, nxs = plan.coarse_shape(0)
+    g = torch.full((nys * nxs,), float("nan"), device="cuda")
+    vd = None if views is None else dev(views, np.int32)
+    b, yp, xp = dev(bs[0]).reshape(-1), dev(y_prev).reshape(-1), dev(x_prev).reshape(-1)
+    xo, yo = torch.empty(n * n, device="cuda"), torch.empty(n * n, device="cuda")
+    say(f"stored gradient, f = {fc}, subsets {subsets}")
+    fbpnp.pnp_step(plan, fbpnp.pnp_args(plan, 0, b, yp, xp, xo, yo, eta, 0.3, vd, sigma, 0.9, grad=g))
+    ref = oracle.grad(og, y_prev, bs[0], fc, views, sigma)[::fc, ::fc] * (fc * fc) / sigma
+    assert rel(host(g).reshape(nys, nxs), ref) <= 1e-5, rel(host(g).reshape(nys, nxs), ref)
+    xbar = dev(rng.standard_normal((n, n)).astype(np.float32)).reshape(-1)
+    ybar = dev(rng.standard_normal((n, n)).astype(np.float32)).reshape(-1)
+    ws = fbpnp.pnp_vjp_workspace(plan)
+    out = []
+    for grad in (g, None):
+        args = fbpnp.pnp_args(plan, 0, b, yp, xp, xp, yp, eta, 0.3, vd, sigma, 0.9, grad=grad)
+        r = (torch.empty(n * n, device="cuda"), torch.empty(n * n, device="cuda"), torch.zeros(1, device="cuda"))
+        fbpnp.pnp_step_vjp(plan, args, xbar, ybar, r[0], r[1], r[2], ws)
+        out.append([host(t) for t in r])
+    for a_, b_ in zip(*out):
+        assert np.array_equal(a_, b_)
+
+
+def test_step_grad_checkpoint_is_refused_where_it_does_not_apply():
+    """grad is stored for minibatch steps with the pooling sketch only."""
+    gd, og, xts, bs = make_problem(32, 16, 48, 31)
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [2, 1])
+    b = dev(bs[0]).reshape(-1)
+    y = torch.zeros(32 * 32, device="cuda")
+    x, xo, yo = y.clone(), y.clone(), y.clone()
+    g = torch.zeros(16 * 16, device="cuda")
+    snap_p = torch.zeros(16 * 48, device="cuda")
+    args = fbpnp.pnp_args(plan, 0, b, y, x, xo, yo, 1e-3, 0.0, vr_mode=1, snap_proj=snap_p, snap_grad=g.clone(),
+                          grad=g)
+    with pytest.raises(fbpnp.FbError):
+        fbpnp.pnp_step(plan, args)
+    plan.set_sketch("bicubic")
+    with pytest.raises(fbpnp.FbError):
+        fbpnp.pnp_step(plan, fbpnp.pnp_args(plan, 0, b, y, x, xo, yo, 1e-3, 0.0, grad=g))
+
+
 def test_unrolled_gradients_coarse_factor_three():
     """8 unrolled iterations at 60^2, 4 at f = 3 then 4 at f = 1, 1 of 5 view subsets: the reverse
     pass pools and back-projects with a factor that divides neither TV tile."""
