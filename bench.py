@@ -515,9 +515,10 @@ def main() -> int:
                 t += 1
         return out
 
-    def make_steps(sched, hist=None, events=None, vr=None, snaps=None):
+    def make_steps(sched, hist=None, events=None, vr=None, snaps=None, stamps=None):
         """pnp_step arguments; vr (optional): per-step variance-reduction mode, with
-        snaps[f] = (snapshot projection, snapshot coarse gradient) per stage."""
+        snaps[f] = (snapshot projection, snapshot coarse gradient) per stage; stamps
+        (optional): int64 device buffer, one end-of-step clock stamp per step."""
         steps = []
         for t, (f, s, a_t) in enumerate(sched):
             mode = 0 if vr is None else vr[t]
@@ -527,7 +528,8 @@ def main() -> int:
             sp, sg = (None, None) if mode == 0 else snaps[f]
             steps.append(fbpnp.pnp_args(plan, stage_of[f], b, y, x, x, y, eta[f], a_t, None, sigma, w.alpha, w.lam,
                                         w.tau, w.tv_iters, None if hist is None else hist[t],
-                                        None if events is None else events[t], mode, sp, sg, subset=sub))
+                                        None if events is None else events[t], mode, sp, sg, subset=sub,
+                                        stamp=None if stamps is None else stamps[t:t + 1]))
         return steps
 
     sk_sched = schedule(w.stages, 3000 * w.seed_base, n_sub)
@@ -785,7 +787,10 @@ def differentiation_section(torch, fbpnp, synth, tune_cache, reps=3, tune_only=F
 def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x, y, xt, T, tune_cache):
     """Per-iteration PSNR (from an iterate history) against cumulative GPU time, for the
     sketched schedule (minibatch and variance-reduced gradients), full-gradient PnP-FISTA
-    and full-resolution PnP-SGD."""
+    and full-resolution PnP-SGD. Each iteration's time comes from its step's clock stamp
+    (the device clock when its denoiser kernel finished) against the previous one, over
+    five replays of the method's stage graphs from the same start state (median per
+    iteration); the first iteration starts at a clock mark written just before them."""
     N = w.n
     npix = N * N
     ref = torch.from_numpy(xt).cuda().reshape(1, -1).double()
@@ -808,8 +813,9 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
         # variance reduction: an epoch of n_sub iterations opens with a full-view snapshot step
         modes = [1 if (i - a) % n_sub_used == 0 else 2 for a, bnd in stage_blocks for i in range(a, bnd)] if vr \
             else None
+        stamps = torch.zeros(len(sched) + 1, dtype=torch.int64, device="cuda")
         graphs = [fbpnp.Graph(plan, make_steps(sched[a:b], hist[a:b], None, None if modes is None else modes[a:b],
-                                               snaps)) for a, b in stage_blocks]
+                                               snaps, stamps[a + 1:b + 1])) for a, b in stage_blocks]
         if x_init is None:
             x.zero_()
             y.zero_()
@@ -822,21 +828,24 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
         torch.cuda.synchronize()
         psnr = (10 * torch.log10(peak ** 2 / ((hist.double() - ref) ** 2).mean(dim=1))).cpu().numpy()
         final = (x.clone(), y.clone())
-        # timing: each stage graph replayed 5 times from the same start state (work is data-independent)
-        per_iter = []
-        for (a, bnd), g in zip(stage_blocks, graphs):
-            times = []
-            for _ in range(5):
-                x.copy_(state0[0])
-                y.copy_(state0[1])
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
+        # timing: the stage graphs replayed back to back 5 times from the same start
+        # state; per-iteration times from the step stamps (device clock, khz ticks/ms)
+        khz = fbpnp.clock_khz()
+        if khz <= 0:
+            raise RuntimeError("time-to-PSNR: the device clock rate is unknown")
+        reps = []
+        for _ in range(5):
+            x.copy_(state0[0])
+            y.copy_(state0[1])
+            stamps.zero_()
+            fbpnp.clock_stamp(stamps[0:1])
+            for g in graphs:
                 g.launch()
-                e1.record()
-                e1.synchronize()
-                times.append(e0.elapsed_time(e1))
-            per_iter += [float(np.median(times)) / (bnd - a)] * (bnd - a)
+            torch.cuda.synchronize()
+            reps.append(np.diff(stamps.cpu().numpy().astype(np.float64)) / khz)
+        per_iter = np.median(np.stack(reps), axis=0)
+        if not (per_iter > 0).all():
+            raise RuntimeError("time-to-PSNR: a step stamp is missing or out of order")
         cum = np.cumsum(per_iter)
         for g in graphs:
             g.close()
@@ -1010,8 +1019,9 @@ def batched_section(torch, fbpnp, synth, steps, tune_cache, tune_only=False):
 def psnr_vs_time(torch, fbpnp, plan, stage_of, b, xt, blocks, eta, alpha, lam, tau, tv_iters, reps=5):
     """Runs consecutive stage blocks [(f, iterations)] from x = y = 0 with FISTA momentum
     (t global), one captured graph per block with an iterate history; returns per-iteration
-    PSNR against xt and cumulative GPU time (each block's graph replayed `reps` times, the
-    median per iteration; the work does not depend on the values)."""
+    PSNR against xt and cumulative GPU time (the graphs replayed back to back `reps` times
+    from the same start, each iteration's time from its step's clock stamp against the
+    previous one, the median per iteration)."""
     from paper_2203_07308_amd import synth
 
     ny, nx = xt.shape
@@ -1021,30 +1031,37 @@ def psnr_vs_time(torch, fbpnp, plan, stage_of, b, xt, blocks, eta, alpha, lam, t
     x = torch.zeros(npix, device="cuda")
     y = torch.zeros(npix, device="cuda")
     hist = torch.empty((T, npix), device="cuda")
+    stamps = torch.zeros(T + 1, dtype=torch.int64, device="cuda")
     graphs, t = [], 0
     for f, n in blocks:
         steps = [fbpnp.pnp_args(plan, stage_of[f], b, y, x, x, y, eta[f], float(a[t + i]), None, 1.0, alpha, lam, tau,
-                                tv_iters, hist[t + i]) for i in range(n)]
-        graphs.append((n, fbpnp.Graph(plan, steps)))
+                                tv_iters, hist[t + i], stamp=stamps[t + i + 1:t + i + 2]) for i in range(n)]
+        graphs.append(fbpnp.Graph(plan, steps))
         t += n
-    for _, g in graphs:
+    for g in graphs:
         g.launch()
     torch.cuda.synchronize()
     ref = torch.from_numpy(xt).cuda().reshape(1, -1).double()
     peak = float(xt.max() - xt.min())
     psnr = (10 * torch.log10(peak ** 2 / ((hist.double() - ref) ** 2).mean(dim=1))).cpu().numpy()
-    per_iter = []
-    for n, g in graphs:
-        times = []
-        for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
+    khz = fbpnp.clock_khz()
+    if khz <= 0:
+        raise RuntimeError("psnr_vs_time: the device clock rate is unknown")
+    runs = []
+    for _ in range(reps):
+        x.zero_()
+        y.zero_()
+        stamps.zero_()
+        fbpnp.clock_stamp(stamps[0:1])
+        for g in graphs:
             g.launch()
-            e1.record()
-            e1.synchronize()
-            times.append(e0.elapsed_time(e1))
-        per_iter += [float(np.median(times)) / n] * n
+        torch.cuda.synchronize()
+        runs.append(np.diff(stamps.cpu().numpy().astype(np.float64)) / khz)
+    for g in graphs:
         g.close()
+    per_iter = np.median(np.stack(runs), axis=0)
+    if not (per_iter > 0).all():
+        raise RuntimeError("psnr_vs_time: a step stamp is missing or out of order")
     return psnr, np.cumsum(per_iter)
 
 

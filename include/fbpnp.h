@@ -255,8 +255,15 @@ fb_status tv_prox_noalloc(const float* z, float* x, int nx, int ny, float lambda
  * sigma grad; pnp_step_vjp reads it back instead of recomputing it (a
  * checkpoint for reverse mode; it must come from the forward step at the same
  * inputs).
+ * stamp (optional): device uint64; every work-group of the step's denoiser
+ * kernel raises it (atomic max) to the device's constant-rate clock
+ * (fb_clock_khz ticks per millisecond) when it has issued its stores, so it
+ * ends as the time the denoiser kernel finished. Clear it before the step.
+ * Consecutive steps' stamps give per-iteration times inside a graph, where
+ * events do not bracket kernels. (With a next-stage pooling factor that does
+ * not divide the TV tile, the pooling runs as a launch after the stamp.)
  * Every optional field (history, events, vr_mode and its buffers, n_sub,
- * subset, grad) means "not used" at zero: zero-initialise the struct
+ * subset, grad, stamp) means "not used" at zero: zero-initialise the struct
  * (fb_pnp_args a = {0}) and set the fields in use.
  */
 typedef struct fb_pnp_args {
@@ -280,8 +287,15 @@ typedef struct fb_pnp_args {
     float* snap_grad;
     int32_t n_sub, subset;
     float* grad;
+    uint64_t* stamp;
 } fb_pnp_args;
 fb_status pnp_step(const fb_plan* plan, const fb_pnp_args* args, hipStream_t stream);
+/* Rate of the device clock behind fb_pnp_args.stamp on the current device, in
+ * kHz (ticks per millisecond); 0 if the runtime does not report it. */
+int32_t fb_clock_khz(void);
+/* Writes the same clock to *dst (device uint64) when the stream reaches this
+ * call (a one-thread kernel): the start mark before a run of stamped steps. */
+fb_status fb_clock_stamp(uint64_t* dst, hipStream_t stream);
 
 /*
  * A whole schedule of pnp_step calls captured once into a HIP graph and

@@ -769,6 +769,8 @@ __device__ __forceinline__ void bps_body(int blk, const RayRec* __restrict__ ray
 //           x_out = x; hist (optional) = x
 //   p_in/p_out: optional global dual field [2][ny][nx] for multi-launch runs
 //   (p_out set: the launch stores p for its tile instead of producing x).
+//   stamp (optional): raised to the device clock (wall_clock64) at which each
+//   work-group finishes, so that it ends as the launch's last such time.
 // ---------------------------------------------------------------------------
 // Tile (bx, by) of the TV-prox, NT threads. Each thread owns vertical pairs
 // of cells (rows 2i, 2i+1 of one column of the haloed tile): their dual
@@ -783,7 +785,7 @@ __device__ __forceinline__ void tv_body(int bx, int by, const float* __restrict_
                                         const float* __restrict__ x_prev, float* __restrict__ x_out,
                                         float* __restrict__ y_out, float* __restrict__ hist, int pf, float pinv,
                                         float* __restrict__ plx, int ppx, float* __restrict__ ply, int ppy,
-                                        int pnxs, int pnys) {
+                                        int pnxs, int pnys, unsigned long long* __restrict__ stamp = nullptr) {
     constexpr int S = T + 2 * H;
     static_assert(S % 2 == 0, "pairs of rows need an even tile side");
     constexpr int NPAIR = (S / 2) * S;
@@ -993,6 +995,12 @@ __device__ __forceinline__ void tv_body(int bx, int by, const float* __restrict_
             plx[(size_t)C * ppx + kPad + R] = sum;
             ply[(size_t)R * ppy + kPad + C] = sum;
         }
+    }
+    if (stamp) {
+        // the device's constant-rate clock when this work-group has issued all its
+        // stores; the latest over the launch marks the end of the step
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(stamp, (unsigned long long)wall_clock64());
     }
 }
 

@@ -178,7 +178,7 @@ struct PoolTarget {
 fb_status launch_tv_single(const float* z, int nx, int ny, float lam, float tau, int n_iter, const float* p_in,
                            float* p_out, int mode, float alpha, float a_t, const float* x_prev, float* x_out,
                            float* y_out, float* hist, hipStream_t s, const PoolTarget& pt = PoolTarget(),
-                           int tile = 0);
+                           int tile = 0, unsigned long long* stamp = nullptr);
 
 // Bicubic sketch (plans with sketch == 1, stages with f > 1): S of x into the
 // stage's line images (or into v when v is set), and out = yprev - scale S^T g

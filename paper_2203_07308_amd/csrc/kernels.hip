@@ -99,11 +99,12 @@ __global__ __launch_bounds__(NT) void k_tv(const float* __restrict__ z, int nx, 
                                            int mode, float alpha, float a_t, const float* __restrict__ x_prev,
                                            float* __restrict__ x_out, float* __restrict__ y_out,
                                            float* __restrict__ hist, int pf, float pinv, float* __restrict__ plx,
-                                           int ppx, float* __restrict__ ply, int ppy, int pnxs, int pnys) {
+                                           int ppx, float* __restrict__ ply, int ppy, int pnxs, int pnys,
+                                           unsigned long long* __restrict__ stamp) {
     const int tile = dev::xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     dev::tv_body<T, H, NT>(tile % gridDim.x, tile / gridDim.x, z, nx, ny, lam, tau, n_iter, p_in, p_out, mode, alpha,
                            a_t, x_prev,
-                           x_out, y_out, hist, pf, pinv, plx, ppx, ply, ppy, pnxs, pnys);
+                           x_out, y_out, hist, pf, pinv, plx, ppx, ply, ppy, pnxs, pnys, stamp);
 }
 
 // ---------------------------------------------------------------------------
@@ -127,6 +128,9 @@ __global__ __launch_bounds__(256) void k_up(const float* __restrict__ v, int nxs
     if (c >= nx || r >= ny) return;
     x[(size_t)r * nx + c] = v[(size_t)(r / f) * nxs + c / f] * inv_ff;
 }
+
+// The device's constant-rate clock, written once (a start mark for step stamps).
+__global__ void k_stamp(unsigned long long* __restrict__ d) { *d = wall_clock64(); }
 
 __global__ __launch_bounds__(256) void k_fill(float* __restrict__ a, size_t n, float val) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -480,13 +484,14 @@ fb_status capture_graph(const std::function<fb_status(hipStream_t)>& body, fb_gr
 
 fb_status launch_tv_single(const float* z, int nx, int ny, float lam, float tau, int n_iter, const float* p_in,
                            float* p_out, int mode, float alpha, float a_t, const float* x_prev, float* x_out,
-                           float* y_out, float* hist, hipStream_t s, const PoolTarget& pt, int tile) {
+                           float* y_out, float* hist, hipStream_t s, const PoolTarget& pt, int tile,
+                           unsigned long long* stamp) {
     const int T = tile ? tile : default_tv_tile((long)cdiv(nx, 32) * cdiv(ny, 32));
     if (pt.f > 0 && T % pt.f != 0) return fail(FB_EINVAL, "pooling factor does not divide the TV tile");
     dim3 grid(cdiv(nx, T), cdiv(ny, T));
 #define FB_TV(TT, HH, NT)                                                                                     \
     FB_LAUNCH((k_tv<TT, HH, NT>), grid, dim3(NT), s, z, nx, ny, lam, tau, n_iter, p_in, p_out, mode, alpha, a_t, \
-              x_prev, x_out, y_out, hist, pt.f, pt.inv, pt.lx, pt.px, pt.ly, pt.py, pt.nxs, pt.nys)
+              x_prev, x_out, y_out, hist, pt.f, pt.inv, pt.lx, pt.px, pt.ly, pt.py, pt.nxs, pt.nys, stamp)
     if (T == 16) {
         if (n_iter <= 5) FB_TV(16, 6, 256);
         else FB_TV(16, kTvMaxFused + 1, 256);
@@ -795,7 +800,8 @@ static fb_status step_tv(const fb_plan* p, const fb_pnp_args* a, hipStream_t str
     {
         TimedLaunch tl(a->events, 4);
         st = launch_tv_single(p->zbuf, p->g.nx, p->g.ny, lam, a->tau, iters, nullptr, nullptr, 1, a->alpha, a->a_t,
-                              a->x_prev, a->x_out, a->y_out, a->history, stream, pt, tile);
+                              a->x_prev, a->x_out, a->y_out, a->history, stream, pt, tile,
+                              reinterpret_cast<unsigned long long*>(a->stamp));
     }
     if (st != FB_OK || !pool_after) return st;
     return launch_prepare(p, a->next_stage, a->y_out, p->g.nx, p->stages[a->next_stage].f, stream);
@@ -866,6 +872,19 @@ fb_status pnp_step(const fb_plan* p, const fb_pnp_args* a, hipStream_t stream) {
             return st;
     }
     return step_tv(p, a, stream);
+}
+
+fb_status fb_clock_stamp(uint64_t* dst, hipStream_t stream) {
+    if (!dst) return fail(FB_EINVAL, "fb_clock_stamp: dst is NULL");
+    k_stamp<<<1, 1, 0, stream>>>(reinterpret_cast<unsigned long long*>(dst));
+    return check_launch("fb_clock_stamp");
+}
+
+int32_t fb_clock_khz(void) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+    return khz;
 }
 
 fb_status fb_graph_create(const fb_plan* p, const fb_pnp_args* steps, int n_steps, fb_graph** out) {

@@ -29,7 +29,7 @@ EXPORTS = [
     "fb_batch_layout", "fb_batch_slice_plan", "fb_batch_set_config", "fb_batch_get_config", "fb_batch_prepare",
     "pnp_step_batched",
     "fb_batch_graph_create", "fb_autotune", "fb_batch_autotune", "fb_plan_set_sketch", "fb_plan_sketch_down",
-    "fb_plan_sketch_up", "tv_prox_noalloc",
+    "fb_plan_sketch_up", "tv_prox_noalloc", "fb_clock_khz", "fb_clock_stamp",
 ]
 
 
@@ -65,6 +65,7 @@ class PnpArgs(ctypes.Structure):
         ("events", ctypes.POINTER(ctypes.c_void_p)),
         ("vr_mode", ctypes.c_int32), ("snap_proj", ctypes.c_void_p), ("snap_grad", ctypes.c_void_p),
         ("n_sub", ctypes.c_int32), ("subset", ctypes.c_int32), ("grad", ctypes.c_void_p),
+        ("stamp", ctypes.c_void_p),
     ]
 
 
@@ -143,6 +144,8 @@ def load() -> ctypes.CDLL:
     lib.fb_pnp_vjp_workspace_bytes.argtypes = [vp, c_int]
     lib.fb_pnp_vjp_workspace_bytes.restype = ctypes.c_size_t
     lib.pnp_step_vjp.argtypes = [vp, P(PnpArgs), vp, vp, vp, vp, vp, c_int, vp, ctypes.c_size_t, vp]
+    lib.fb_clock_khz.argtypes = []
+    lib.fb_clock_stamp.argtypes = [vp, vp]
     for name in EXPORTS:
         if name not in ("fb_last_error", "fb_tv_workspace_bytes", "fb_tv_vjp_workspace_bytes",
                         "fb_pnp_vjp_workspace_bytes"):
@@ -349,7 +352,7 @@ def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float
              tau: float = 0.125, tv_iters: int = 5, history: torch.Tensor | None = None,
              events=None, vr_mode: int = 0, snap_proj: torch.Tensor | None = None,
              snap_grad: torch.Tensor | None = None, subset: tuple[int, int] | None = None,
-             grad: torch.Tensor | None = None) -> PnpArgs:
+             grad: torch.Tensor | None = None, stamp: torch.Tensor | None = None) -> PnpArgs:
     """Arguments of one pnp_step. events: optional sequence of six torch.cuda.Event
     (enable_timing=True) or None, recorded around the step's fp, bp and TV kernels.
     vr_mode 1 / 2 with snap_proj [n_views * n_bins] and snap_grad (the stage's coarse
@@ -357,7 +360,9 @@ def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float
     subset = (k, n_sub), with views None: the interleaved subset k, k + n_sub, ...
     of the views, whose indices the kernels compute instead of reading a list.
     grad (the stage's coarse image size): pnp_step stores the coarse gradient there,
-    and pnp_step_vjp reads it back instead of recomputing it."""
+    and pnp_step_vjp reads it back instead of recomputing it.
+    stamp: one int64 element (a view into a zeroed buffer) that receives the device
+    clock at which the step's denoiser kernel finished (see clock_khz)."""
     npix = plan.geom.nx * plan.geom.ny
     if subset is not None and views is not None:
         raise ValueError("pnp_args: give views or subset, not both")
@@ -379,6 +384,10 @@ def pnp_args(plan: Plan, stage: int, b, y_prev, x_prev, x_out, y_out, eta: float
     if grad is not None:
         nys, nxs = plan.coarse_shape(stage)
         a.grad = _ptr(grad, numel=nxs * nys, name="grad")
+    if stamp is not None:
+        if stamp.dtype != torch.int64 or not stamp.is_cuda or stamp.numel() < 1:
+            raise ValueError("stamp: need a CUDA int64 tensor with at least one element")
+        a.stamp = stamp.data_ptr()
     if events is not None:
         if len(events) != 6:
             raise ValueError("events: need six entries (fp, bp, TV; begin and end)")
@@ -395,6 +404,18 @@ def chain_steps(steps) -> None:
     for a, b in zip(steps[:-1], steps[1:]):
         if b.y_prev == a.y_out:
             a.next_stage, b.prepared = b.stage, 1
+
+
+def clock_khz() -> int:
+    """Ticks per millisecond of the device clock behind step stamps (0 if unknown)."""
+    return int(load().fb_clock_khz())
+
+
+def clock_stamp(dst: torch.Tensor, stream=None) -> None:
+    """Writes the device clock to dst (one CUDA int64 element) when the stream gets there."""
+    if dst.dtype != torch.int64 or not dst.is_cuda or dst.numel() < 1:
+        raise ValueError("clock_stamp: need a CUDA int64 tensor with at least one element")
+    _check(load().fb_clock_stamp(ctypes.c_void_p(dst.data_ptr()), _stream(stream)))
 
 
 def pnp_step(plan: Plan, args: PnpArgs, stream=None) -> None:

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     text = open(os.path.join(ROOT, "include", "fbpnp.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return re.findall(r"^\s*(?:fb_status|size_t|const char\*)\s+(\w+)\s*\(", text, flags=re.M)
+    return re.findall(r"^\s*(?:fb_status|size_t|int32_t|const char\*)\s+(\w+)\s*\(", text, flags=re.M)
 
 
 def test_library_exports_every_declared_symbol():
@@ -114,8 +114,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fb_geom), offsetof(fb_geom, angle_step_rad),
          sizeof(fb_stage_info), sizeof(fb_pnp_args), offsetof(fb_pnp_args, b),
          offsetof(fb_pnp_args, tv_iters), offsetof(fb_pnp_args, history), offsetof(fb_pnp_args, events));
-  printf("%zu %zu %zu\\n", offsetof(fb_pnp_args, vr_mode), offsetof(fb_pnp_args, snap_grad),
-         offsetof(fb_pnp_args, grad));
+  printf("%zu %zu %zu %zu\\n", offsetof(fb_pnp_args, vr_mode), offsetof(fb_pnp_args, snap_grad),
+         offsetof(fb_pnp_args, grad), offsetof(fb_pnp_args, stamp));
   printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(fb_launch_config), sizeof(fb_batch_args), offsetof(fb_batch_args, eta),
          offsetof(fb_batch_args, tv_iters), offsetof(fb_batch_args, history), offsetof(fb_batch_args, events));
   return 0;
@@ -129,6 +129,7 @@ int main(void) {
             ctypes.sizeof(fbpnp.PnpArgs), fbpnp.PnpArgs.b.offset, fbpnp.PnpArgs.tv_iters.offset,
             fbpnp.PnpArgs.history.offset, fbpnp.PnpArgs.events.offset,
             fbpnp.PnpArgs.vr_mode.offset, fbpnp.PnpArgs.snap_grad.offset, fbpnp.PnpArgs.grad.offset,
+            fbpnp.PnpArgs.stamp.offset,
             ctypes.sizeof(fbpnp.LaunchConfig), ctypes.sizeof(fbpnp.BatchArgs), fbpnp.BatchArgs.eta.offset,
             fbpnp.BatchArgs.tv_iters.offset, fbpnp.BatchArgs.history.offset, fbpnp.BatchArgs.events.offset]
     assert got == want

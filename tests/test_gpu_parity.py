@@ -393,10 +393,11 @@ def problem(name, seed=0):
 
 
 def run_gpu(plan, gd, b, sched, eta, a, alpha=1.0, lam=0.01, history=False, graph=False, chained=False,
-            events=None, tv_iters=5):
+            events=None, tv_iters=5, stamps=None):
     """Runs the schedule with pnp_step (or as one captured graph). sched: (stage_index, views, sigma).
     chained: direct calls with the graph's pooling hand-over; events: list that receives six
-    timing events per step."""
+    timing events per step; stamps: zeroed int64 device buffer of len(sched) + 1 (a clock
+    mark, then one end-of-step stamp per step)."""
     npix = gd["nx"] * gd["ny"]
     bd = dev(b)
     xb = torch.zeros(npix, device="cuda")
@@ -412,9 +413,12 @@ def run_gpu(plan, gd, b, sched, eta, a, alpha=1.0, lam=0.01, history=False, grap
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
             events.append(ev)
         steps.append(fbpnp.pnp_args(plan, s, bd, yb, xb, xb, yb, float(eta[t]), float(a[t]), dv, sigma,
-                                    alpha, lam, 0.125, tv_iters, None if hist is None else hist[t], ev))
+                                    alpha, lam, 0.125, tv_iters, None if hist is None else hist[t], ev,
+                                    stamp=None if stamps is None else stamps[t + 1:t + 2]))
     if chained:
         fbpnp.chain_steps(steps)
+    if stamps is not None:
+        fbpnp.clock_stamp(stamps[0:1])
     if graph:
         g = fbpnp.Graph(plan, steps)
         g.launch()
@@ -615,6 +619,34 @@ def test_graph_replay_equals_eager_and_is_deterministic():
         for k in (0, 2, 4):
             ms = ev[k].elapsed_time(ev[k + 1])
             assert 0.0 < ms < 50.0, ms
+
+
+def test_step_stamps_mark_each_step_end_and_change_nothing():
+    """With stamps, each step records the device clock when its denoiser kernel finished: after the
+    start mark, strictly increasing, spanning no more than the events around the run; the iterates are
+    bitwise those of the unstamped run (direct calls and graph)."""
+    w, gd, og, xt, b = problem("pnp64")
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [2, 1])
+    sub = synth.subset_views(0, 4, gd["n_views"])
+    sched = [(0, sub, 4.0)] * 3 + [(1, None, 1.0)] * 3
+    eta = np.full(6, 1e-4)
+    a = synth.momentum_table(6)
+    khz = fbpnp.clock_khz()
+    assert khz > 0
+    say("step stamps")
+    ref = run_gpu(plan, gd, b, sched, eta, a, graph=True)
+    for graph in (False, True):
+        stamps = torch.zeros(7, dtype=torch.int64, device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = run_gpu(plan, gd, b, sched, eta, a, graph=graph, stamps=stamps)
+        e1.record()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out, ref)
+        st = host(stamps).astype(np.int64)
+        assert st[0] > 0 and (np.diff(st) > 0).all(), st
+        span_ms = (st[-1] - st[0]) / khz
+        assert 0.0 < span_ms <= e0.elapsed_time(e1) * 1.05 + 0.01, (span_ms, e0.elapsed_time(e1))
 
 
 def test_side_stream_equals_default_stream():
