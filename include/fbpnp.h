@@ -290,7 +290,8 @@ typedef struct fb_pnp_args {
     uint64_t* stamp;
 } fb_pnp_args;
 fb_status pnp_step(const fb_plan* plan, const fb_pnp_args* args, hipStream_t stream);
-/* Rate of the device clock behind fb_pnp_args.stamp on the current device, in
+/* Measurement of the time to reach a PSNR (the comparison of Sec. 3):
+ * rate of the device clock behind fb_pnp_args.stamp on the current device, in
  * kHz (ticks per millisecond); 0 if the runtime does not report it. */
 int32_t fb_clock_khz(void);
 /* Writes the same clock to *dst (device uint64) when the stream reaches this
