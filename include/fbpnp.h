@@ -168,8 +168,10 @@ fb_status fanbeam_fp(const fb_plan* plan, int stage, const float* x, float* y, c
 
 /*
  * Matched backprojection x = scale * (M A_s)^T y: the exact transpose of
- * fanbeam_fp (identical interpolation weights), computed as a pixel-driven
- * gather with no atomics, so results are bitwise reproducible.
+ * fanbeam_fp (identical interpolation weights), computed without atomics (a
+ * pixel-driven gather or, with bp_px 16 or 32, a scatter into per-wavefront
+ * LDS blocks whose concurrent lanes never share a cell, added in a fixed
+ * order), so results are bitwise reproducible.
  *   y: device [n_sel][n_bins]; x: device [nys][nxs], overwritten.
  */
 fb_status fanbeam_bp(const fb_plan* plan, int stage, const float* y, float* x, const int32_t* views,
