@@ -800,7 +800,7 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
     snaps = {f: (torch.zeros(V * B, device="cuda"), torch.zeros((N // f) ** 2, device="cuda"))
              for f, _ in w.stages}
 
-    def run(stages, n_sub_used, seed, t_offset=0, x_init=None, vr=False):
+    def run(stages, n_sub_used, seed, t_offset=0, x_init=None, vr=False, vr_epoch=None):
         # each method runs with the launch configurations tuned for its view count
         plan.autotune(n_sel=w.n_views // n_sub_used if n_sub_used else w.n_views, cache_path=tune_cache)
         sched = schedule(stages, seed, n_sub_used, True, t_offset)
@@ -810,9 +810,11 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
         for f, n in stages:
             stage_blocks.append((t, t + n))
             t += n
-        # variance reduction: an epoch of n_sub iterations opens with a full-view snapshot step
-        modes = [1 if (i - a) % n_sub_used == 0 else 2 for a, bnd in stage_blocks for i in range(a, bnd)] if vr \
-            else None
+        # variance reduction: an epoch of vr_epoch iterations (default n_sub) opens with a
+        # full-view snapshot step; vr_epoch 0: one snapshot at each stage start only
+        ep = n_sub_used if vr_epoch is None else vr_epoch
+        modes = [1 if (i == a if ep == 0 else (i - a) % ep == 0) else 2
+                 for a, bnd in stage_blocks for i in range(a, bnd)] if vr else None
         stamps = torch.zeros(len(sched) + 1, dtype=torch.int64, device="cuda")
         graphs = [fbpnp.Graph(plan, make_steps(sched[a:b], hist[a:b], None, None if modes is None else modes[a:b],
                                                snaps, stamps[a + 1:b + 1])) for a, b in stage_blocks]
@@ -856,6 +858,7 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
     ps_sgd, t_sgd, _ = run([(1, T)], w.n_subsets, seed + 1)
     ps_sk, t_sk, fin = run(w.stages, w.n_subsets, seed)
     ps_vr, t_vr, _ = run(w.stages, w.n_subsets, seed, vr=True)
+    ps_vr0, t_vr0, _ = run(w.stages, w.n_subsets, seed, vr=True, vr_epoch=0)
     # extend the sketched run's final stage (same subset stream rule) up to 240 iterations
     ext_p, ext_t = [ps_sk], [t_sk]
     p_star = float(ps_full[-1])
@@ -873,6 +876,7 @@ def time_to_psnr(torch, fbpnp, synth, w, plan, stage_of, schedule, make_steps, x
 
     out = {"p_star_db": round(p_star, 3), "definition": "P* = PSNR of full-gradient PnP-FISTA after 60 iterations"}
     for name, ps, ts in (("sketched_ms2g", ps_sk_all, t_sk_all), ("sketched_ms2g_svrg", ps_vr, t_vr),
+                         ("sketched_ms2g_svrg_stage_snapshots", ps_vr0, t_vr0),
                          ("full_pnp_fista", ps_full, t_full), ("full_res_pnp_sgd", ps_sgd, t_sgd)):
         out[name] = {
             "iterations": int(len(ps)), "final_psnr_db": round(float(ps[-1]), 3),
