@@ -41,7 +41,7 @@ OPS_PER_BP_FINE_PIXEL = 2   # z = y_prev - scale * (U g)
 OPS_PER_TV_PIXEL_ITER = 30
 OPS_PER_TV_PIXEL_OUT = 8    # final divergence, relaxation, momentum
 GATHER_BYTES_PER_SAMPLE = 8  # the two 4-byte interpolation taps of a Joseph sample
-KERNEL_DESCRIPTION = {"fp": "Joseph forward projection minus b", "bp": "matched gather back-projection fused with the "
+KERNEL_DESCRIPTION = {"fp": "Joseph forward projection minus b", "bp": "matched back-projection fused with the "
                       "gradient step", "tv": "TV-prox with relaxation, momentum and pooling epilogue"}
 KERNEL_SOURCES = ["paper_2203_07308_amd/csrc/" + f for f in
                   ("device.h", "kernels.hip", "fbpnp_impl.h", "plan.cpp", "tune.cpp")]
@@ -74,9 +74,29 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def launch_traffic(key: str, path: str | None = None):
+def launch_kernel(kind: str, cfg: dict, tv_iters: int = 5) -> str:
+    """Template name of the kernel that one launch of a fused step runs ("fp", "bp" or
+    "tv") under the launch configuration cfg (fb_launch_config fields, as get_config
+    returns them), as rocprofv3 names it: the back-projector's gather (bp_px 1, 2, 4) or
+    scatter form (bp_px 16, 32), the projector's global or LDS taps."""
+    if kind == "fp":
+        return ("k_fp_lds" if cfg["fp_lds"] == 2 else "k_fp") + f"<true, {cfg['fp_seg']}>"
+    if kind == "bp":
+        if cfg["bp_px"] >= 16:
+            return f"k_bps<{cfg['bp_px']}, {cfg['bp_vg']}, true>"
+        return f"k_bp<{cfg['bp_vg']}, {cfg['bp_px']}, true, false>"
+    t = cfg["tv_tile"]
+    return f"k_tv<{t}, {6 if tv_iters <= 5 else 9}, {1024 if t == 32 else 256}>"
+
+
+def bp_form(cfg: dict) -> str:
+    return "scatter" if cfg["bp_px"] >= 16 else "gather"
+
+
+def launch_traffic(key: str, path: str | None = None, kernel: str | None = None):
     """HBM bytes per launch of kernel group `key` (e.g. "bp_f1") from the committed
-    counter summary, or None when it is missing or was taken from other kernel sources."""
+    counter summary, or None when it is missing, was taken from other kernel sources,
+    or (with kernel) was measured on another kernel than the one named."""
     import re
 
     path = path or os.path.join(ROOT, TRAFFIC_SUMMARY)
@@ -86,10 +106,12 @@ def launch_traffic(key: str, path: str | None = None):
     m = re.search(r"kernel sources sha256: `([0-9a-f]{64})`", text)
     if not m or m.group(1) != kernel_source_hash():
         return None, "counter summary predates the current kernel sources"
-    m = re.search(r"^\| " + re.escape(key) + r" \|(?:[^|\n]*\|){6}\s*([0-9]+)\s*\|", text, re.M)
+    m = re.search(r"^\| " + re.escape(key) + r" \| ([^|\n]*)\|(?:[^|\n]*\|){5}\s*([0-9]+)\s*\|", text, re.M)
     if not m:
         return None, f"no {key} row in the counter summary"
-    return int(m.group(1)), TRAFFIC_SUMMARY
+    if kernel is not None and m.group(1).strip() != f"`{kernel}`":
+        return None, f"counter summary measured {m.group(1).strip()} for {key}, not `{kernel}`"
+    return int(m.group(2)), TRAFFIC_SUMMARY
 
 
 def log(*a):
@@ -191,7 +213,7 @@ def label_dispatches(names, grids=None):
     w = synth.WORKLOADS["ms2g512"]
     stage_f = [f for f, n in w.stages for _ in range(n)]
     T = len(stage_f)
-    want = ("k_fp<true", "k_bp<", "k_tv<")
+    want = (("k_fp<true", "k_fp_lds<true"), ("k_bp<", "k_bps<"), ("k_tv<",))
     out = []
     i = 0
     while i < len(names):
@@ -626,7 +648,7 @@ def main() -> int:
     # launch time) and its share of the HBM roof; and the same for the timed kernels of a step
     step_bytes, step_us, complete = 0, 0.0, True
     for k, v in kernels.items():
-        t_k, _ = launch_traffic(k)
+        t_k, _ = launch_traffic(k, kernel=launch_kernel(k[:2], configs[k[3:]], w.tv_iters))
         if t_k:
             rate = t_k / (v["avg_launch_us"] * 1e-6) / 1e9
             v.update(hbm_bytes_per_launch=t_k, hbm_gb_per_s=rate, hbm_frac=rate / PEAK_HBM_GBS)
@@ -643,8 +665,12 @@ def main() -> int:
     for k, v in kernels.items():
         log(f"  {k}: {v}")
     dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["us_per_step"])
-    traffic, traffic_src = launch_traffic(dom_name)
-    roofline = {"kernel": f"{dom_name} ({KERNEL_DESCRIPTION[dom_name[:2]]}, pooling factor {dom_name[4:]})",
+    dom_cfg = configs[dom_name[3:]]
+    dom_kernel = launch_kernel(dom_name[:2], dom_cfg, w.tv_iters)
+    traffic, traffic_src = launch_traffic(dom_name, kernel=dom_kernel)
+    form = f", {bp_form(dom_cfg)} form" if dom_name.startswith("bp") else ""
+    roofline = {"kernel": f"{dom_name} ({KERNEL_DESCRIPTION[dom_name[:2]]}{form}, pooling factor {dom_name[4:]}): "
+                          f"{dom_kernel}",
                 "bound": "alu", "achieved": round(dom["tflops"], 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(dom["tflops"] / PEAK_FP32_TFLOPS, 5), "traffic": traffic,
                 "traffic_source": traffic_src,

@@ -5,13 +5,15 @@ import os
 import bench
 
 
-def schedule_names(n_replays=2):
+def schedule_names(n_replays=2, scatter_f1=False):
     names = ["fill", "fill"]
     for _ in range(n_replays):
         names.append("k_prepare")
         for t in range(60):
             f = (4, 2, 1)[t // 20]
-            names += ["k_fp<true, 4>", f"k_bp<{16 if f > 1 else 8}, {1 if f == 4 else 2}, true>", "k_tv<32, 6, 1024>"]
+            bp = "k_bps<32, 16, true>" if scatter_f1 and f == 1 else \
+                f"k_bp<{16 if f > 1 else 8}, {1 if f == 4 else 2}, true>"
+            names += ["k_fp<true, 4>", bp, "k_tv<32, 6, 1024>"]
         names += ["fill", "fill"]
     names.append("__amd_rocclr_copyBuffer")
     return names
@@ -37,11 +39,39 @@ def test_label_dispatches_groups_every_replay():
     assert bench.label_dispatches(tuning + names) == [(g, j + len(tuning)) for g, j in lab]
 
 
+def test_label_dispatches_accepts_the_scatter_back_projector():
+    names = schedule_names(2, scatter_f1=True)
+    lab = bench.label_dispatches(names)
+    groups = {}
+    for g, j in lab:
+        groups.setdefault(g, []).append(j)
+    assert len(lab) == 2 * 181
+    assert all(names[j].startswith("k_bps<32, 16") for j in groups["bp_f1"])
+    assert all(names[j].startswith("k_bp<") for j in groups["bp_f2"])
+
+
+def test_launch_kernel_names_follow_the_launch_configuration():
+    c = dict(fp_seg=8, bp_px=2, bp_vg=16, tv_tile=32, fp_lds=1)
+    assert bench.launch_kernel("fp", c) == "k_fp<true, 8>"
+    assert bench.launch_kernel("bp", c) == "k_bp<16, 2, true, false>"
+    assert bench.launch_kernel("tv", c) == "k_tv<32, 6, 1024>"
+    assert bench.launch_kernel("tv", c, tv_iters=7) == "k_tv<32, 9, 1024>"
+    s = dict(c, bp_px=32, fp_lds=2, tv_tile=16)
+    assert bench.launch_kernel("bp", s) == "k_bps<32, 16, true>"
+    assert bench.launch_kernel("fp", s) == "k_fp_lds<true, 8>"
+    assert bench.launch_kernel("tv", s) == "k_tv<16, 6, 256>"
+    assert bench.bp_form(c) == "gather" and bench.bp_form(s) == "scatter"
+
+
 def test_launch_traffic_reads_matching_summary(tmp_path):
     p = tmp_path / "t.md"
     row = "| bp_f1 | `k_bp<8, 2, true>` | 40 | 5210.4 | 1024.0 | 10666042 | 1048576 | 11714618 |"
     p.write_text(f"kernel sources sha256: `{bench.kernel_source_hash()}`\n\n{row}\n")
     assert bench.launch_traffic("bp_f1", str(p))[0] == 11714618
+    assert bench.launch_traffic("bp_f1", str(p), kernel="k_bp<8, 2, true>")[0] == 11714618
+    # a row measured on another launch form of the group is not used
+    t, why = bench.launch_traffic("bp_f1", str(p), kernel="k_bps<32, 16, true>")
+    assert t is None and "k_bps<32, 16, true>" in why
     assert bench.launch_traffic("fp_f1", str(p))[0] is None
     p.write_text(f"kernel sources sha256: `{'0' * 64}`\n\n{row}\n")
     assert bench.launch_traffic("bp_f1", str(p))[0] is None
