@@ -4,7 +4,8 @@ runs (the shipped autotuner cache), against the FP64 oracle:
   * the 512^2 multi-stage sketched PnP-SGD schedule (Algorithm 1, Option 2): 720 views x
     768 bins, 20 iterations each at f = 4, 2, 1, 1 of 8 interleaved view subsets drawn from
     the benchmark's seeded stream, per-stage steps 1 / L, FISTA momentum, all 60 iterations
-    as one captured graph;
+    as one captured graph; and the same problem with every view per gradient, in the launch
+    shapes tuned for all 720 views (f = 4, then f = 1);
   * the 64-slice batched workload (widths 128 to 512, 180 / 360 / 720 views, 1.5 x width
     bins, two-stage sketch) with its tuned batch configuration: every slice bitwise equal to
     the same slice run alone, and two slices (384^2 x 720 views, 512^2 x 360 views) against
@@ -114,6 +115,45 @@ def test_ms2g512_whole_schedule_as_benchmarked(tmp_path):
     assert max(errs) <= 1e-4, (int(np.argmax(errs)), max(errs))
     # the reconstruction improves on the data: the schedule does what it is for
     assert oracle.psnr(ref, xt) > 30.0
+
+
+def test_ms2g512_all_views_in_the_tuned_launch_shapes(tmp_path):
+    """The 512^2 problem with every view in each gradient (the full-gradient PnP-FISTA run of the
+    time-to-PSNR comparison), in the launch shapes the shipped cache holds for 720 selected
+    views: 3 iterations at f = 4, then 4 at f = 1, steps 1 / L, FISTA momentum, by direct
+    pnp_step calls, each iterate against the oracle's."""
+    w = synth.WORKLOADS["ms2g512"]
+    gd = w.geometry
+    og = oracle.Geometry(**gd)
+    V = gd["n_views"]
+    xt = synth.phantom(w)
+    ax = oracle.fp(og, xt.astype(np.float64))
+    b = synth.add_noise(ax, synth.standard_normal(synth.noise_seed(w), ax.shape), w.noise_kind,
+                        w.noise_level).astype(np.float32)
+    L = oracle_lipschitz()
+    factors = [4, 1]
+    fs = [4] * 3 + [1] * 4
+    T = len(fs)
+    eta = np.array([1.0 / L[("ms2g512", f)] for f in fs])
+    a = synth.momentum_table(T, True)
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), factors)
+    plan.autotune(n_sel=V, cache_path=tuned_cache(tmp_path))
+    say("ms2g512 all views", [plan.get_config(k, V) for k in range(len(factors))])
+    npix = gd["nx"] * gd["ny"]
+    bd = dev(b).reshape(-1)
+    x = torch.zeros(npix, device="cuda")
+    y = torch.zeros(npix, device="cuda")
+    hist = torch.zeros((T, npix), device="cuda")
+    for t in range(T):
+        fbpnp.pnp_step(plan, fbpnp.pnp_args(plan, factors.index(fs[t]), bd, y, x, x, y, float(eta[t]), float(a[t]),
+                                            None, 1.0, w.alpha, w.lam, w.tau, w.tv_iters, hist[t]))
+    got_hist = host(hist)
+    sched_o = [(f, None, 1.0) for f in fs]
+    ref, ref_hist = oracle.pnp_run(og, b.astype(np.float64), sched_o, eta, a, w.alpha, w.lam, w.tv_iters, w.tau,
+                                   history=True)
+    errs = [rel(got_hist[t].reshape(ref.shape), ref_hist[t]) for t in range(T)]
+    say("ms2g512 all views, error per iterate", errs)
+    assert max(errs) <= 1e-4, (int(np.argmax(errs)), max(errs))
 
 
 BATCH_ORACLE_SLICES = (3, 24)  # 384^2 x 720 views and 512^2 x 360 views
