@@ -57,7 +57,7 @@ typedef int fb_status;
 #define FB_EINVAL (-1)  /* null pointer, non-positive size, bad stage or parameter */
 #define FB_EGEOM (-2)   /* geometry not valid (source inside the image circle, fan too wide, non-finite) */
 #define FB_EDIV (-3)    /* image size not divisible by the pooling factor */
-#define FB_ESUBSET (-4) /* view list too long */
+#define FB_ESUBSET (-4) /* view list too long, or (fb_check_views) an index outside the views */
 #define FB_EHIP (-5)    /* HIP runtime or launch error (message holds the HIP text) */
 #define FB_ENOMEM (-6)  /* device allocation failed (plan or graph creation only) */
 
@@ -159,12 +159,25 @@ fb_status fb_plan_get_config(const fb_plan* plan, int stage, int n_sel, fb_launc
  *   views: device int32 list of n_sel view indices (the rows of M), or NULL
  *     for all views in order (then n_sel must equal n_views). Repeats are
  *     allowed; an index outside [0, n_views) yields a zero row (fp) or no
- *     contribution (bp); indices are not checked on the host.
+ *     contribution (bp); indices are not checked here (fb_check_views does).
  *   y: device [n_sel][n_bins], overwritten.
  * Uses the plan workspace.
  */
 fb_status fanbeam_fp(const fb_plan* plan, int stage, const float* x, float* y, const int32_t* views,
                      int n_sel, hipStream_t stream);
+
+/*
+ * Checks a device view list (the rows of M_k, Sec. 2.1, Eq. (7)) against the
+ * plan, as a set-up call for callers that want it: the calls above and
+ * pnp_step read the list on the device and give a zero row for an index outside
+ * [0, n_views) instead.
+ *   views: device int32 [n_sel]; n_sel >= 1.
+ * Returns FB_ESUBSET when n_sel exceeds n_views or an index lies outside
+ * [0, n_views) (fb_last_error() names the first such position and its value),
+ * FB_EINVAL for a NULL pointer or n_sel < 1, FB_OK otherwise. Allocates 4 bytes
+ * of device memory for the call and synchronises the stream.
+ */
+fb_status fb_check_views(const fb_plan* plan, const int32_t* views, int32_t n_sel, hipStream_t stream);
 
 /*
  * Matched backprojection x = scale * (M A_s)^T y: the exact transpose of

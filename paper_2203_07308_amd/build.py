@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfbpnp.so")
-SOURCES = [os.path.join(CSRC, n) for n in ("kernels.hip", "batch.hip", "bicubic.hip", "vjp.hip", "tune.cpp", "plan.cpp")]
+SOURCES = [os.path.join(CSRC, n) for n in ("kernels.hip", "batch.hip", "bicubic.hip", "vjp.hip", "views.hip", "tune.cpp", "plan.cpp")]
 ARCH = os.environ.get("FBPNP_ARCH", "gfx950")
 
 FLAGS = [

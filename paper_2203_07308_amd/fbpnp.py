@@ -21,7 +21,8 @@ _STATUS = {-1: "FB_EINVAL", -2: "FB_EGEOM", -3: "FB_EDIV", -4: "FB_ESUBSET", -5:
 
 # every exported entry point, in the order of include/fbpnp.h
 EXPORTS = [
-    "fb_last_error", "fb_plan_create", "fb_plan_destroy", "fb_plan_stage_info", "fanbeam_fp", "fanbeam_bp",
+    "fb_last_error", "fb_plan_create", "fb_plan_destroy", "fb_plan_stage_info", "fanbeam_fp", "fb_check_views",
+    "fanbeam_bp",
     "sketch_down", "sketch_up", "fb_tv_workspace_bytes", "tv_prox", "pnp_step", "fb_graph_create",
     "fb_graph_launch", "fb_graph_destroy", "fb_tv_vjp_workspace_bytes", "tv_prox_vjp",
     "fb_pnp_vjp_workspace_bytes", "pnp_step_vjp", "fb_power_lipschitz", "fb_plan_view_samples",
@@ -144,6 +145,7 @@ def load() -> ctypes.CDLL:
     lib.fb_pnp_vjp_workspace_bytes.argtypes = [vp, c_int]
     lib.fb_pnp_vjp_workspace_bytes.restype = ctypes.c_size_t
     lib.pnp_step_vjp.argtypes = [vp, P(PnpArgs), vp, vp, vp, vp, vp, c_int, vp, ctypes.c_size_t, vp]
+    lib.fb_check_views.argtypes = [vp, vp, c_int, vp]
     lib.fb_clock_khz.argtypes = []
     lib.fb_clock_stamp.argtypes = [vp, vp]
     for name in EXPORTS:
@@ -297,6 +299,13 @@ def fanbeam_fp(plan: Plan, stage: int, x: torch.Tensor, y: torch.Tensor, views: 
     _check(load().fanbeam_fp(plan.handle, stage, _ptr(x, numel=nx * ny, name="x"),
                              _ptr(y, numel=n_sel * plan.geom.n_bins, name="y"), vp, n_sel, _stream(stream)))
     return y
+
+
+def check_views(plan: Plan, views: torch.Tensor, stream=None) -> None:
+    """fb_check_views: raises FbError (FB_ESUBSET) if the device view list holds an index
+    outside [0, n_views) or more entries than views; synchronises the stream."""
+    vp, n_sel = _views(plan, views)
+    _check(load().fb_check_views(plan.handle, vp, n_sel, _stream(stream)))
 
 
 def fanbeam_bp(plan: Plan, stage: int, y: torch.Tensor, x: torch.Tensor, views: torch.Tensor | None = None,

@@ -209,6 +209,31 @@ def test_fanbeam_bp_skips_invalid_views():
         assert rel(host(x).reshape(ref.shape), ref) <= 1e-5, form
 
 
+def test_check_views_reports_the_first_index_outside_the_views():
+    """fb_check_views: FB_ESUBSET naming the first bad position and its value, for indices
+    below 0 and at or above n_views, and for a list longer than the views; valid lists
+    (repeats included) pass. A 720-view plan checks a list spread over several blocks."""
+    gd, og, plan, _ = setup_case("ragged", 1, None)
+    V = gd["n_views"]
+    fbpnp.check_views(plan, dev(np.array([0, V - 1, 3, 3], dtype=np.int32), np.int32))
+    fbpnp.check_views(plan, dev(np.arange(V, dtype=np.int32)[::-1].copy(), np.int32))
+    for lst, pos, val in (([36, -1, 17, 37, 1 << 20], 1, -1), ([2, 5, V], 2, V)):
+        with pytest.raises(fbpnp.FbError) as e:
+            fbpnp.check_views(plan, dev(np.array(lst, dtype=np.int32), np.int32))
+        assert e.value.status == -4 and f"views[{pos}] = {val} " in str(e.value), str(e.value)
+    with pytest.raises(fbpnp.FbError) as e:
+        fbpnp.check_views(plan, dev(np.zeros(V + 1, dtype=np.int32), np.int32))
+    assert e.value.status == -4
+    big = fbpnp.Plan(fbpnp.Geometry(**synth.WORKLOADS["ms2g512"].geometry), [4])
+    W = big.geom.n_views
+    lst = np.arange(W, dtype=np.int32) % 97
+    fbpnp.check_views(big, dev(lst, np.int32))
+    lst[650], lst[300], lst[601] = -7, W + 3, W
+    with pytest.raises(fbpnp.FbError) as e:
+        fbpnp.check_views(big, dev(lst, np.int32))
+    assert e.value.status == -4 and f"views[300] = {W + 3} " in str(e.value), str(e.value)
+
+
 @pytest.mark.parametrize("name,f", [("256", 1), ("512", 4), ("ragged", 2), ("512", 1), ("widefan", 1),
                                     ("finepitch", 1)])
 def test_fp32_adjoint_identity(name, f):
