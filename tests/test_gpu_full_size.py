@@ -11,12 +11,14 @@ runs (the shipped autotuner cache), against the FP64 oracle:
     the same slice run alone, and two slices (384^2 x 720 views, 512^2 x 360 views) against
     the oracle over 5 iterations per stage;
   * the paper's three 256^2 scan scenarios (Sec. 3) over their whole 25 + 75 two-stage
-    schedule.
+    schedule;
+  * a 4096^2 grid, and the refusal of a grid past the 32-bit line-image offsets.
 
 Reconstruction bar: relative L2 <= 1e-4 (the reconstruction tolerance of the path). The
 oracle's step sizes for the two larger problems come from tests/golden/oracle_step_sizes.txt
 (written by the oracle alone; 100 power iterations at 512^2 take minutes of host time).
 """
+import math
 import os
 import shutil
 import sys
@@ -154,6 +156,67 @@ def test_ms2g512_all_views_in_the_tuned_launch_shapes(tmp_path):
     errs = [rel(got_hist[t].reshape(ref.shape), ref_hist[t]) for t in range(T)]
     say("ms2g512 all views, error per iterate", errs)
     assert max(errs) <= 1e-4, (int(np.argmax(errs)), max(errs))
+
+
+def test_largest_grids():
+    """A 4096^2 grid (6 views x 6144 bins, stages f = 8 and 1): each view's projection at both
+    stages, the back-projection in the gather and scatter forms, and two fused steps (f = 8,
+    then f = 1) against the oracle; and a grid whose two line images would need byte offsets
+    beyond 32 bits is refused when the plan is created, before anything is launched."""
+    n = 4096
+    gd = synth.fan_geometry(n, 6, 6144)
+    og = oracle.Geometry(**gd)
+    plan = fbpnp.Plan(fbpnp.Geometry(**gd), [8, 1])
+    c = (np.arange(n) - (n - 1) / 2) / n
+    xt = ((c[None, :] ** 2 + c[:, None] ** 2 < 0.16) * (1.0 + 0.5 * c[None, :] - 0.3 * c[:, None])).astype(np.float32)
+    rng = np.random.default_rng(17)
+    for k, f in enumerate((8, 1)):
+        xs = oracle.down(xt, f)
+        ref = oracle.fp(og, xs, f)
+        y = torch.empty(6 * gd["n_bins"], device="cuda")
+        say("largest fp", f)
+        fbpnp.fanbeam_fp(plan, k, dev(xs).reshape(-1), y)
+        got = host(y).reshape(ref.shape)
+        per_view = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        assert per_view.max() <= 1e-5, (f, per_view.max())
+        r = (rng.random(ref.shape) - 0.3).astype(np.float32)
+        refb = oracle.bp(og, r.astype(np.float64), f, None, 1.0)
+        # A sample's position p (|p| < n / 2f in centred pixels) is rounded to float once, so
+        # its two weights carry an error of rms ulp(p) / sqrt(12), which a back-projected
+        # pixel (a sum of a few samples) keeps, while a projection (a sum of thousands)
+        # averages it down; the bar is three times that rms at the largest |p|, and 1e-5
+        # below it (up to 512^2).
+        tol_bp = max(1e-5, 3.0 * 2.0 ** (math.ceil(math.log2(n / (2 * f))) - 24) / math.sqrt(12.0))
+        for form in (None, dict(fp_seg=0, bp_px=2, bp_vg=16, tv_tile=0), dict(fp_seg=0, bp_px=32, bp_vg=16, tv_tile=0)):
+            plan.set_config(k, form)
+            xb = torch.empty((n // f) * (n // f), device="cuda")
+            say("largest bp", f, form)
+            fbpnp.fanbeam_bp(plan, k, dev(r).reshape(-1), xb)
+            err = rel(host(xb).reshape(refb.shape), refb)
+            say("largest bp error", f, form, err, "bar", tol_bp)
+            assert err <= tol_bp, (f, form, err, tol_bp)
+        plan.set_config(k, None)
+    b = oracle.fp(og, xt.astype(np.float64)).astype(np.float32)
+    L = oracle.power_lipschitz(og, 8, 10)
+    eta, a = np.array([1.0 / L, 1.0 / L]), synth.momentum_table(2, True)
+    bd = dev(b).reshape(-1)
+    x = torch.zeros(n * n, device="cuda")
+    yv = torch.zeros(n * n, device="cuda")
+    hist = torch.zeros((2, n * n), device="cuda")
+    for t, k in enumerate((0, 1)):
+        say("largest step", t)
+        fbpnp.pnp_step(plan, fbpnp.pnp_args(plan, k, bd, yv, x, x, yv, float(eta[t]), float(a[t]), None, 1.0,
+                                            1.0, 0.01, 0.125, 5, hist[t]))
+    got = host(hist)
+    _, ref_hist = oracle.pnp_run(og, b.astype(np.float64), [(8, None, 1.0), (1, None, 1.0)], eta, a, history=True)
+    errs = [rel(got[t].reshape(n, n), ref_hist[t]) for t in range(2)]
+    say("largest steps, error per iterate", errs)
+    assert max(errs) <= 1e-4, errs
+    # 2 x 23200 x 23204 floats of line images: byte offsets past 2^31
+    too_big = synth.fan_geometry(23200, 1, 8)
+    with pytest.raises(fbpnp.FbError) as e:
+        fbpnp.Plan(fbpnp.Geometry(**too_big), [1])
+    assert e.value.status == -1 and "32-bit" in str(e.value)
 
 
 BATCH_ORACLE_SLICES = (3, 24)  # 384^2 x 720 views and 512^2 x 360 views
