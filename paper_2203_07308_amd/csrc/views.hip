@@ -32,8 +32,9 @@ extern "C" fb_status fb_check_views(const fb_plan* p, const int32_t* views, int3
                                     std::to_string(p->g.n_views));
     int* d = nullptr;
     if (hipMalloc(&d, sizeof(int)) != hipSuccess) return fail(FB_ENOMEM, "fb_check_views: device allocation failed");
+    static const int kNone = INT_MAX;  // the initial value (a copy source that outlives the call)
     int first = INT_MAX, bad = 0;
-    hipError_t e = hipMemcpyAsync(d, &first, sizeof(int), hipMemcpyHostToDevice, stream);
+    hipError_t e = hipMemcpyAsync(d, &kNone, sizeof(int), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) {
         k_check_views<<<(n_sel + 255) / 256, 256, 0, stream>>>(views, n_sel, p->g.n_views, d);
         e = hipGetLastError();
