@@ -194,6 +194,40 @@ def test_fanbeam_bp_matches_oracle(name, f, sel):
             assert rel(got, ref) <= tol, (form, rel(got, ref))
 
 
+@pytest.mark.parametrize("form", [dict(fp_seg=0, bp_px=32, bp_vg=16, tv_tile=0),
+                                  dict(fp_seg=0, bp_px=16, bp_vg=16, tv_tile=0)])
+def test_scatter_bp_repeats_bit_for_bit_at_512(form):
+    """The scatter back-projector at 512^2, f = 1, on a 90-view subset (the benchmarked
+    full-resolution shape): five launches give the same bits, as a lost update between
+    lanes of one wavefront would not, and match the oracle. Also fused, inside pnp_step:
+    repeated steps from the same inputs give the same bits."""
+    gd, og, plan, views = setup_case("512", 1, ("sub", 5, 8))
+    plan.set_config(0, form)
+    rng = np.random.default_rng(23)
+    y = (rng.random((len(views), gd["n_bins"])) - 0.4).astype(np.float32)
+    ref = oracle.bp(og, y.astype(np.float64), 1, views, 1.0)
+    dv, dy = dev(views, np.int32), dev(y)
+    outs = []
+    for _ in range(5):
+        x = torch.empty(gd["nx"] * gd["ny"], device="cuda")
+        fbpnp.fanbeam_bp(plan, 0, dy, x, dv)
+        outs.append(host(x))
+    say("scatter repeat", form, rel(outs[0].reshape(ref.shape), ref))
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    assert rel(outs[0].reshape(ref.shape), ref) <= 2e-5
+    b = dev(rng.random((gd["n_views"], gd["n_bins"])).astype(np.float32))
+    yp = dev(ellipse_image(gd["ny"], gd["nx"], 5).astype(np.float32))
+    xp = yp.clone()
+    zs = []
+    for _ in range(3):
+        xo, yo = torch.empty_like(yp), torch.empty_like(yp)
+        fbpnp.pnp_step(plan, fbpnp.pnp_args(plan, 0, b, yp, xp, xo, yo, 1e-6, 0.5, dv, 8.0))
+        zs.append(host(xo))
+    for z in zs[1:]:
+        np.testing.assert_array_equal(z, zs[0])
+
+
 def test_fanbeam_bp_skips_invalid_views():
     """View indices outside [0, n_views) add nothing and repeats add twice, in every launch shape."""
     gd, og, plan, _ = setup_case("ragged", 1, None)
