@@ -93,6 +93,20 @@ def bp_form(cfg: dict) -> str:
     return "scatter" if cfg["bp_px"] >= 16 else "gather"
 
 
+# what limits each launch form on this GPU, read from its counters (SQ_INSTS_VALU, VALU
+# busy, SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT in the committed counter summary); the roofline
+# itself stays on the survey's ALU accounting (operations per sample against the FP32 peak)
+LIMITER = {
+    "bp_scatter": "LDS: one read-add-write of both taps per sample into per-wavefront block copies, "
+                  "with bank conflicts (VALU about 0.6 busy)",
+    "bp_gather": "VALU issue at full resolution (candidate ranges and per-candidate weights); "
+                 "the dependent chain of views per wavefront at the coarse stages",
+    "fp": "address and L2 request rate of the scattered tap loads at full resolution; each "
+          "wavefront's dependent chain at the coarse stages",
+    "tv": "latency of loads, LDS exchanges and barriers between dual steps",
+}
+
+
 def launch_traffic(key: str, path: str | None = None, kernel: str | None = None):
     """HBM bytes per launch of kernel group `key` (e.g. "bp_f1") from the committed
     counter summary, or None when it is missing, was taken from other kernel sources,
@@ -669,6 +683,7 @@ def main() -> int:
     dom_kernel = launch_kernel(dom_name[:2], dom_cfg, w.tv_iters)
     traffic, traffic_src = launch_traffic(dom_name, kernel=dom_kernel)
     form = f", {bp_form(dom_cfg)} form" if dom_name.startswith("bp") else ""
+    limiter = LIMITER["bp_" + bp_form(dom_cfg)] if dom_name.startswith("bp") else LIMITER[dom_name[:2]]
     roofline = {"kernel": f"{dom_name} ({KERNEL_DESCRIPTION[dom_name[:2]]}{form}, pooling factor {dom_name[4:]}): "
                           f"{dom_kernel}",
                 "bound": "alu", "achieved": round(dom["tflops"], 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -678,7 +693,8 @@ def main() -> int:
                 "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
                 "frac_nonpacked": round(dom["tflops"] / PEAK_FP32_NONPACKED_TFLOPS, 5),
                 "avg_launch_us": round(dom["avg_launch_us"], 3),
-                "flop_per_launch": round(dom["flop_per_launch"]), "launches_timed": dom["launches_per_step"] * reps}
+                "flop_per_launch": round(dom["flop_per_launch"]), "launches_timed": dom["launches_per_step"] * reps,
+                "limiter": limiter}
     if traffic:
         # the measured HBM rate of the dominant kernel and its share of the HBM roof
         hbm = traffic / (dom["avg_launch_us"] * 1e-6) / 1e12
