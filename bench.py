@@ -101,7 +101,8 @@ LIMITER = {
                   "with bank conflicts (VALU about 0.6 busy)",
     "bp_gather": "VALU issue at full resolution (candidate ranges and per-candidate weights); "
                  "the dependent chain of views per wavefront at the coarse stages",
-    "fp": "address and L2 request rate of the scattered tap loads at full resolution; each "
+    "fp": "the scattered tap loads through L1 and L2 at full resolution (their width, lanes per "
+          "address and loads in flight each change the time by at most 7 percent); each "
           "wavefront's dependent chain at the coarse stages",
     "tv": "latency of loads, LDS exchanges and barriers between dual steps",
 }
