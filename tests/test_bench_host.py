@@ -50,6 +50,17 @@ def test_label_dispatches_accepts_the_scatter_back_projector():
     assert all(names[j].startswith("k_bp<") for j in groups["bp_f2"])
 
 
+def test_label_dispatches_accepts_the_lds_tap_projector():
+    names = schedule_names(1)
+    names = [("k_fp_lds<true, 8>" if n.startswith("k_fp") and i < 2 + 1 + 60 else n) for i, n in enumerate(names)]
+    lab = bench.label_dispatches(names)
+    assert len(lab) == 181
+    assert all(names[j].startswith("k_fp_lds") for g, j in lab if g == "fp_f4")
+    # an untimed projection (no residual) is not part of an iteration
+    bad = [("k_fp<false, 8>" if n.startswith("k_fp") else n) for n in names]
+    assert bench.label_dispatches(bad) == []
+
+
 def test_launch_kernel_names_follow_the_launch_configuration():
     c = dict(fp_seg=8, bp_px=2, bp_vg=16, tv_tile=32, fp_lds=1)
     assert bench.launch_kernel("fp", c) == "k_fp<true, 8>"
